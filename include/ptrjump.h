@@ -1,0 +1,176 @@
+/*
+ * ptrjump -- pointer jumping over int32 successor and parent arrays on one
+ * AMD Instinct MI355X (gfx950): list ranking and connected components.
+ *
+ * Method: Dehne & Yogaratnam, "Exploring the Limits of GPUs With Parallel
+ * Graph Algorithms".  List ranking follows the problem statement of Section 3,
+ * solved either by Wyllie's pointer jumping (Section 3.1) or by the parallel
+ * random-splitter (sparse ruling set) method of Reid-Miller (Section 3.2,
+ * Algorithm "Parallel Random Splitter"), whose splitter list is itself ranked
+ * recursively.  Connected components follow Section 4: a hook-and-shortcut
+ * algorithm of the Shiloach-Vishkin family with the step split of the
+ * paper's SV-GPU (shortcut and mark separated by a barrier, conditional and
+ * stagnant-star hooking, shortcut, change flag), with labels canonicalised to
+ * the smallest vertex id of each component.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Array arguments are DEVICE pointers owned by the caller, unless the name
+ *    starts with h_ (host pointer).  The library never frees them.
+ *  - Calls are asynchronous on `stream` (NULL = the default stream); outputs
+ *    are valid once the stream reaches the call.  The return value reports
+ *    argument errors detected on the host before anything is enqueued, and HIP
+ *    errors; 0 means enqueued.
+ *  - Errors in the DATA (a successor array that is not one list per instance,
+ *    a solve that does not converge) are found on the device.  They are
+ *    written to opts->d_status when given (one int32 per instance); with
+ *    opts->validate != 0 and no d_status, the call waits for the stream and
+ *    returns the status itself.  Whatever the input, every kernel stays in
+ *    bounds and terminates.
+ *  - Ids are int32; counts are int64 but an instance (and a whole batch) must
+ *    hold fewer than 2^31 nodes or vertices.
+ *  - Temporary device memory is taken stream-ordered from the device's memory
+ *    pool (hipMallocAsync / hipFreeAsync) unless the caller passes a workspace
+ *    of at least *_workspace_bytes() bytes in opts->workspace.
+ */
+#ifndef PTRJUMP_H
+#define PTRJUMP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same type as HIP's hipStream_t. */
+typedef struct ihipStream_t *pj_stream_t;
+
+/* ----------------------------------------------------------- status codes */
+#define PJ_OK 0
+#define PJ_EINVAL (-1)    /* bad argument (null pointer, negative or too large size, aliasing) */
+#define PJ_ENOMEM (-2)    /* device memory could not be obtained */
+#define PJ_EHIP (-3)      /* a HIP runtime call failed (see pj_last_hip_error) */
+#define PJ_EBADLIST (-4)  /* the successor array is not exactly one list over the instance */
+#define PJ_ENOCONV (-5)   /* components did not converge within the round guard */
+#define PJ_EBUDGET (-6)   /* serving: request larger than the whole HBM budget */
+#define PJ_ENOTFOUND (-7) /* serving: unknown request id */
+#define PJ_EBUSY (-8)     /* serving: request not finished yet (poll again) */
+#define PJ_ESHUTDOWN (-9) /* serving: server is shutting down */
+
+/* ------------------------------------------------------------- algorithms */
+#define PJ_ALGO_AUTO 0        /* tuned choice (ruling set for lists, SV for components) */
+#define PJ_ALGO_WYLLIE 1      /* list ranking by pointer jumping, ceil(log2 n) device-wide rounds */
+#define PJ_ALGO_RULING_SET 2  /* list ranking by random splitters with recursive splitter ranking */
+#define PJ_ALGO_SV 3          /* components: Shiloach-Vishkin hook and shortcut */
+
+#define PJ_MAX_PHASES 16
+#define PJ_MAX_LEVELS 8
+
+/* Per-call options.  Zero-initialise (or call pj_opts_init) and set what you
+ * need; every zero field means "library default / tuned value". */
+typedef struct pj_opts {
+    int32_t algo;             /* PJ_ALGO_* */
+    int32_t block;            /* threads per workgroup, multiple of 64 in [64, 1024] */
+    int32_t spacing;          /* ruling set, first level: one splitter per `spacing`
+                                 consecutive node ids (power of two, 2..65536) */
+    int32_t spacing_up;       /* ruling set, recursion levels: same meaning */
+    int32_t cutoff;           /* ruling set: a level with at most this many nodes is ranked
+                                 by one workgroup in LDS (64..8192) */
+    int32_t max_walk;         /* ruling set: a sublist walk is cut after this many nodes,
+                                 the cut node becoming a new splitter (>= 16) */
+    uint64_t seed;            /* splitter hash seed (results do not depend on it) */
+    int32_t validate;         /* 1: run the complete check of the output on the device */
+    int32_t to_tail;          /* 1: list ranks count the distance to the tail (the paper's
+                                 convention) instead of the distance from the head */
+    int32_t rounds_per_check; /* components: rounds enqueued between host convergence checks */
+    int32_t use_graph;        /* batched list ranking: replay a captured hipGraph */
+    int32_t *d_status;        /* optional device int32[instances]: PJ_OK / PJ_EBADLIST / PJ_ENOCONV */
+    void *workspace;          /* optional caller-owned device workspace */
+    size_t workspace_bytes;
+    const int64_t *h_offsets;      /* batched: host copy of the (vertex) offset table */
+    const int64_t *h_edge_offsets; /* batched components: host copy of the edge offsets */
+    struct pj_stats *stats;   /* optional: filled after the call (forces a stream sync) */
+} pj_opts;
+
+/* Diagnostics of one call, filled when opts->stats is set. */
+typedef struct pj_stats {
+    int32_t algo;                 /* algorithm actually run */
+    int32_t levels;               /* ruling set: walk levels (recursion depth) */
+    int32_t base_kind;            /* ruling set: 1 LDS workgroup, 2 device-wide pointer jumping */
+    int32_t rounds;               /* components: Shiloach-Vishkin rounds run */
+    int64_t level_nodes[PJ_MAX_LEVELS + 1]; /* nodes at each level (level 0 = input) */
+    int32_t nphases;
+    char phase_name[PJ_MAX_PHASES][24];
+    float phase_ms[PJ_MAX_PHASES];  /* device time of each phase (HIP events) */
+    int32_t status;               /* first data error found, or PJ_OK */
+} pj_stats;
+
+void pj_opts_init(pj_opts *opts);
+const char *pj_strerror(int code);
+/* Text of the last HIP error seen by the library on this thread. */
+const char *pj_last_hip_error(void);
+int pj_version(void);
+
+/* ---------------------------------------------------------- list ranking */
+/*
+ * List ranking (Section 3 problem statement).  succ[i] is the successor of
+ * node i in [0, n); the tail is marked by succ[i] == -1 or succ[i] == i.
+ * Writes rank[i] = distance of node i from the head (rank[head] = 0), or with
+ * opts->to_tail the distance to the tail, which is the paper's definition.
+ * rank must not alias succ.  n == 0 is a no-op.
+ */
+int pj_list_rank(const int32_t *succ, int64_t n, int32_t *rank, pj_stream_t stream);
+int pj_list_rank_ex(const int32_t *succ, int64_t n, int32_t *rank, const pj_opts *opts,
+                    pj_stream_t stream);
+
+/*
+ * Batched list ranking: L independent lists concatenated.  offsets is a
+ * DEVICE int64[L+1] table (offsets[0] == 0, non-decreasing); list l occupies
+ * [offsets[l], offsets[l+1]) and its successors are LOCAL ids in
+ * [0, size_l) (tail -1 or self).  rank receives local ranks per list.  With
+ * opts->h_offsets the host copy is used for planning and no device->host read
+ * happens; otherwise offsets[L] is read back (the call then synchronises the
+ * stream once).  d_status, when given, holds L entries.
+ */
+int pj_list_rank_batched(const int32_t *succ, const int64_t *offsets, int64_t L, int32_t *rank,
+                         pj_stream_t stream);
+int pj_list_rank_batched_ex(const int32_t *succ, const int64_t *offsets, int64_t L,
+                            int32_t *rank, const pj_opts *opts, pj_stream_t stream);
+
+/* Bytes of workspace a call with these sizes needs (L = 1 for the plain call). */
+size_t pj_list_rank_workspace_bytes(int64_t total_nodes, int64_t L, const pj_opts *opts);
+
+/* ---------------------------------------------------- connected components */
+/*
+ * Connected components (Section 4 problem statement).  src[e], dst[e] for
+ * e in [0, m) are undirected vertex pairs in [0, n); self-loops and
+ * duplicates are allowed.  Writes label[v] = smallest vertex id of v's
+ * component.  label must not alias src or dst.
+ */
+int pj_connected_components(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
+                            int32_t *label, pj_stream_t stream);
+int pj_connected_components_ex(const int32_t *src, const int32_t *dst, int64_t n, int64_t m,
+                               int32_t *label, const pj_opts *opts, pj_stream_t stream);
+
+/*
+ * Batched components: G independent graphs.  vtx_off and edge_off are DEVICE
+ * int64[G+1] tables; graph g owns vertices [vtx_off[g], vtx_off[g+1]) and
+ * pairs [edge_off[g], edge_off[g+1]), with LOCAL vertex ids.  label receives
+ * local labels (smallest local id of each component).
+ */
+int pj_connected_components_batched(const int32_t *src, const int32_t *dst,
+                                    const int64_t *vtx_off, const int64_t *edge_off, int64_t G,
+                                    int32_t *label, pj_stream_t stream);
+int pj_connected_components_batched_ex(const int32_t *src, const int32_t *dst,
+                                       const int64_t *vtx_off, const int64_t *edge_off,
+                                       int64_t G, int32_t *label, const pj_opts *opts,
+                                       pj_stream_t stream);
+
+size_t pj_cc_workspace_bytes(int64_t n, int64_t m, int64_t G, const pj_opts *opts);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTRJUMP_H */

@@ -1,0 +1,148 @@
+"""Torch-facing wrappers over the C ABI.
+
+torch supplies device memory and the current HIP stream; these functions only
+check shapes and dtypes, build a pj_opts struct and pass raw pointers.
+"""
+
+from __future__ import annotations
+
+import ctypes
+
+import torch
+
+from . import _lib
+from ._lib import ALGO, PjError, PjOpts, PjStats
+
+
+def _stream_ptr(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_i32(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int32 or not t.is_cuda:
+        raise TypeError(f"{name} must be an int32 CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _dev_i64(t, name):
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.int64 or not t.is_cuda:
+        raise TypeError(f"{name} must be an int64 CUDA/HIP tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None and t.numel() else ctypes.c_void_p(0)
+
+
+def make_opts(algo="auto", block=0, spacing=0, spacing_up=0, cutoff=0, max_walk=0, seed=None,
+              validate=False, to_tail=False, rounds_per_check=0, use_graph=False, status=None,
+              workspace=None, h_offsets=None, h_edge_offsets=None, stats=None):
+    """Build a pj_opts.  Host arrays (h_offsets...) must stay alive for the call."""
+    o = PjOpts()
+    _lib.load().pj_opts_init(ctypes.byref(o))
+    o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
+    o.block = block
+    o.spacing = spacing
+    o.spacing_up = spacing_up
+    o.cutoff = cutoff
+    o.max_walk = max_walk
+    if seed is not None:
+        o.seed = seed
+    o.validate = int(bool(validate))
+    o.to_tail = int(bool(to_tail))
+    o.rounds_per_check = rounds_per_check
+    o.use_graph = int(bool(use_graph))
+    if status is not None:
+        o.d_status = _dev_i32(status, "status").data_ptr()
+    if workspace is not None:
+        o.workspace = workspace.data_ptr()
+        o.workspace_bytes = workspace.numel() * workspace.element_size()
+    if h_offsets is not None:
+        o.h_offsets = h_offsets.ctypes.data
+    if h_edge_offsets is not None:
+        o.h_edge_offsets = h_edge_offsets.ctypes.data
+    if stats is not None:
+        o.stats = ctypes.pointer(stats)
+    return o
+
+
+def _check(rc, where):
+    if rc != _lib.PJ_OK:
+        raise PjError(rc, where)
+
+
+def list_rank(succ, rank=None, *, stream=None, return_stats=False, **kw):
+    """Rank one list: rank[i] = distance of node i from the head (or to the
+    tail with to_tail=True).  `succ` is int32 on the device, tail -1 or self."""
+    succ = _dev_i32(succ, "succ")
+    n = succ.numel()
+    if rank is None:
+        rank = torch.empty_like(succ)
+    _dev_i32(rank, "rank")
+    st = PjStats() if return_stats else None
+    o = make_opts(stats=st, **kw)
+    rc = _lib.load().pj_list_rank_ex(_ptr(succ), n, _ptr(rank), ctypes.byref(o), _stream_ptr(stream))
+    _check(rc, "pj_list_rank")
+    return (rank, st.to_dict()) if return_stats else rank
+
+
+def list_rank_batched(succ, offsets, rank=None, *, h_offsets=None, stream=None,
+                      return_stats=False, **kw):
+    """Rank L lists concatenated in `succ` (local ids) with device int64
+    offsets[L+1]; `h_offsets` (numpy int64) avoids a device-to-host read."""
+    succ = _dev_i32(succ, "succ")
+    offsets = _dev_i64(offsets, "offsets")
+    L = offsets.numel() - 1
+    if rank is None:
+        rank = torch.empty_like(succ)
+    _dev_i32(rank, "rank")
+    st = PjStats() if return_stats else None
+    o = make_opts(stats=st, h_offsets=h_offsets, **kw)
+    rc = _lib.load().pj_list_rank_batched_ex(_ptr(succ), _ptr(offsets), L, _ptr(rank),
+                                             ctypes.byref(o), _stream_ptr(stream))
+    _check(rc, "pj_list_rank_batched")
+    return (rank, st.to_dict()) if return_stats else rank
+
+
+def connected_components(src, dst, n, label=None, *, stream=None, return_stats=False, **kw):
+    """label[v] = smallest vertex id in v's component (device int32 pairs)."""
+    src = _dev_i32(src, "src")
+    dst = _dev_i32(dst, "dst")
+    if src.numel() != dst.numel():
+        raise ValueError("src and dst differ in length")
+    if label is None:
+        label = torch.empty(n, dtype=torch.int32, device=src.device)
+    _dev_i32(label, "label")
+    if label.numel() < n:
+        raise ValueError("label too short")
+    st = PjStats() if return_stats else None
+    o = make_opts(stats=st, **kw)
+    rc = _lib.load().pj_connected_components_ex(_ptr(src), _ptr(dst), n, src.numel(), _ptr(label),
+                                                ctypes.byref(o), _stream_ptr(stream))
+    _check(rc, "pj_connected_components")
+    return (label, st.to_dict()) if return_stats else label
+
+
+def connected_components_batched(src, dst, vtx_off, edge_off, label=None, *, h_vtx_off=None,
+                                 h_edge_off=None, stream=None, return_stats=False, **kw):
+    src = _dev_i32(src, "src")
+    dst = _dev_i32(dst, "dst")
+    vtx_off = _dev_i64(vtx_off, "vtx_off")
+    edge_off = _dev_i64(edge_off, "edge_off")
+    G = vtx_off.numel() - 1
+    if label is None:
+        total = int(h_vtx_off[-1]) if h_vtx_off is not None else int(vtx_off[-1].item())
+        label = torch.empty(total, dtype=torch.int32, device=src.device)
+    _dev_i32(label, "label")
+    st = PjStats() if return_stats else None
+    o = make_opts(stats=st, h_offsets=h_vtx_off, h_edge_offsets=h_edge_off, **kw)
+    rc = _lib.load().pj_connected_components_batched_ex(
+        _ptr(src), _ptr(dst), _ptr(vtx_off), _ptr(edge_off), G, _ptr(label), ctypes.byref(o),
+        _stream_ptr(stream))
+    _check(rc, "pj_connected_components_batched")
+    return (label, st.to_dict()) if return_stats else label

@@ -1,0 +1,477 @@
+// Connected components on gfx950: Shiloach-Vishkin hook and shortcut
+// (Section 4, the paper's SV-GPU), then labels canonicalised to the smallest
+// vertex id of each component.
+//
+// State: parent array D (held in the caller's label buffer), and two round
+// stamps per vertex: NS[r] = s marks root r's tree as not a star in round s,
+// Q[r] = s marks r as involved in a conditional hook in round s.  Stamps
+// avoid clearing the arrays between rounds.
+//
+// Round s, one kernel per step, each kernel boundary a grid-wide barrier:
+//   1a  shortcut          D[v] <- D[D[v]]
+//   1b  mark non-stars    if D[v] != D[D[v]]: NS[D[D[v]]] = s
+//       (1a must be complete for every vertex first, hence two kernels)
+//   2   conditional hook  edge (i,j), a = D[i]: if a is the root of a star and
+//                         b = D[j] < a: D[a] = b, Q[a] = Q[b] = s
+//   3   stagnant hook     if a is the root of a star with Q[a] != s and
+//                         b = D[j] != a: D[a] = b
+//   4   shortcut          D[v] <- D[D[v]]
+//   5   change flag       any non-star mark or hook sets w[s] (an OR by
+//                         concurrent writes); the solve ends after the first
+//                         round with w[s] == 0.
+// Each pair is processed in both orientations by the thread that reads it.
+// Concurrent writes to one root land in arbitrary order; every outcome is
+// one the arbitrary-CRCW algorithm allows: step 2 only hooks star roots onto
+// strictly smaller ids, step 3 only hooks stars that no step-2 hook touched,
+// and two such stars are never adjacent, so no cycle can form.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "pj_internal.hpp"
+
+namespace pj {
+namespace {
+
+struct CcCtl {
+  int32_t err;
+  int32_t rounds;
+};
+
+// The round-s kernels do nothing once an earlier round saw no change.
+__device__ __forceinline__ bool converged(const int32_t* w, int s) { return s > 1 && w[s - 1] == 0; }
+
+__global__ void sv_init(int32_t* __restrict__ D, int32_t* __restrict__ NS, int32_t* __restrict__ Q,
+                        int n, int32_t* w, int wlen, CcCtl* ctl) {
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  for (int v = tid; v < n; v += stride) {
+    D[v] = v;
+    NS[v] = 0;
+    Q[v] = 0;
+  }
+  for (int i = tid; i < wlen; i += stride) w[i] = 0;
+  if (tid == 0) {
+    ctl->err = 0;
+    ctl->rounds = 0;
+  }
+}
+
+// Step 1a and step 4.
+__global__ void __launch_bounds__(256) sv_shortcut(int32_t* __restrict__ D, int n,
+                                                   const int32_t* w, int s) {
+  if (converged(w, s)) return;
+  const int stride = gridDim.x * blockDim.x;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int p = D[v];
+    const int gp = D[p];
+    if (gp != p) D[v] = gp;
+  }
+}
+
+// Step 1b.
+__global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
+                                               int32_t* __restrict__ NS, int n, int32_t* w,
+                                               int s, CcCtl* ctl) {
+  if (converged(w, s)) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rounds = s;
+  const int stride = gridDim.x * blockDim.x;
+  bool changed = false;
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const int p = D[v];
+    const int gp = D[p];
+    if (p != gp) {
+      NS[gp] = s;
+      changed = true;
+    }
+  }
+  if (__ballot(changed) && lane_id() == 0) w[s] = 1;
+}
+
+// Loads of four pairs at a time when the arrays allow it.
+template <typename F>
+__device__ __forceinline__ void for_each_pair(const int32_t* __restrict__ src,
+                                              const int32_t* __restrict__ dst, int64_t m, F f) {
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
+  const int64_t m4 = aligned ? (m >> 2) : 0;
+  const int4* s4 = reinterpret_cast<const int4*>(src);
+  const int4* d4 = reinterpret_cast<const int4*>(dst);
+  for (int64_t q = tid; q < m4; q += stride) {
+    const int4 a = s4[q];
+    const int4 b = d4[q];
+    f(a.x, b.x);
+    f(a.y, b.y);
+    f(a.z, b.z);
+    f(a.w, b.w);
+  }
+  for (int64_t e = (m4 << 2) + tid; e < m; e += stride) f(src[e], dst[e]);
+}
+
+// Step 2.
+__global__ void __launch_bounds__(256) sv_hook(const int32_t* __restrict__ src,
+                                               const int32_t* __restrict__ dst, int64_t m,
+                                               int32_t* __restrict__ D,
+                                               const int32_t* __restrict__ NS,
+                                               int32_t* __restrict__ Q, int n, int32_t* w, int s,
+                                               CcCtl* ctl) {
+  if (converged(w, s)) return;
+  bool hooked = false, bad = false;
+  for_each_pair(src, dst, m, [&](int u, int v) {
+    if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) {
+      bad = true;
+      return;
+    }
+    const int du = D[u];
+    const int dv = D[v];
+    int a, b;
+    if (dv < du) {
+      a = du;
+      b = dv;
+    } else if (du < dv) {
+      a = dv;
+      b = du;
+    } else {
+      return;
+    }
+    if (D[a] == a && NS[a] != s) {
+      D[a] = b;
+      Q[a] = s;
+      Q[b] = s;
+      hooked = true;
+    }
+  });
+  if (__ballot(hooked) && lane_id() == 0) w[s] = 1;
+  if (__ballot(bad) && lane_id() == 0) atomicOr(&ctl->err, kErrRange);
+}
+
+// Step 3.
+__global__ void __launch_bounds__(256) sv_stagnant(const int32_t* __restrict__ src,
+                                                   const int32_t* __restrict__ dst, int64_t m,
+                                                   int32_t* __restrict__ D,
+                                                   const int32_t* __restrict__ NS,
+                                                   const int32_t* __restrict__ Q, int n,
+                                                   int32_t* w, int s) {
+  if (converged(w, s)) return;
+  bool hooked = false;
+  for_each_pair(src, dst, m, [&](int u, int v) {
+    if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) return;
+    const int du = D[u];
+    const int dv = D[v];
+    if (du == dv) return;
+    if (D[du] == du && NS[du] != s && Q[du] != s) {
+      D[du] = dv;
+      hooked = true;
+    } else if (D[dv] == dv && NS[dv] != s && Q[dv] != s) {
+      D[dv] = du;
+      hooked = true;
+    }
+  });
+  if (__ballot(hooked) && lane_id() == 0) w[s] = 1;
+}
+
+// ------------------------------------------------------- canonicalisation
+// After convergence every component is one star.  M[root] = smallest member
+// (M starts as the identity), then label[v] = M[D[v]].  A workgroup folds the
+// members of the root of its first vertex before touching M, so a giant
+// component costs one atomic per workgroup, not one per vertex.
+constexpr int kCanonPerThread = 8;
+
+__global__ void canon_init(int32_t* __restrict__ M, int n) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) M[v] = v;
+}
+
+__global__ void __launch_bounds__(256) canon_min(const int32_t* __restrict__ D,
+                                                 int32_t* __restrict__ M, int n) {
+  __shared__ int lead;
+  __shared__ int wmin[256 / kWave];
+  const int per_block = 256 * kCanonPerThread;
+  for (int64_t c0 = (int64_t)blockIdx.x * per_block; c0 < n; c0 += (int64_t)gridDim.x * per_block) {
+    __syncthreads();
+    if (threadIdx.x == 0) lead = D[c0];
+    __syncthreads();
+    const int leader = lead;
+    int mymin = INT32_MAX;
+#pragma unroll
+    for (int t = 0; t < kCanonPerThread; ++t) {
+      const int64_t v = c0 + t * 256 + threadIdx.x;
+      if (v >= n) break;
+      const int r = D[v];
+      if (r == leader) mymin = min(mymin, (int)v);
+      else atomicMin(&M[r], (int)v);
+    }
+    mymin = wave_min(mymin);
+    if (lane_id() == 0) wmin[threadIdx.x / kWave] = mymin;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int bm = INT32_MAX;
+      for (int i = 0; i < 256 / kWave; ++i) bm = min(bm, wmin[i]);
+      if (bm != INT32_MAX) atomicMin(&M[leader], bm);
+    }
+  }
+}
+
+// label[v] = M[D[v]]; `D` and `label` may be the same array.  In the batched
+// form labels are turned back into local ids.
+template <bool kBatched>
+__global__ void __launch_bounds__(256) canon_label(int32_t* D, const int32_t* __restrict__ M,
+                                                   int n, const int64_t* __restrict__ voff,
+                                                   int G) {
+  for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+    int lab = M[D[v]];
+    if (kBatched) lab -= (int)voff[find_instance(voff, G, v)];
+    D[v] = lab;
+  }
+}
+
+// Batched: rewrite local pairs as global vertex ids (graph g's vertices start
+// at voff[g]).  A pair whose ends leave its graph is made out of range so the
+// rounds skip it and report it.
+__global__ void __launch_bounds__(256) cc_globalise(const int32_t* __restrict__ src,
+                                                    const int32_t* __restrict__ dst,
+                                                    const int64_t* __restrict__ voff,
+                                                    const int64_t* __restrict__ eoff, int G,
+                                                    int64_t m, int32_t* __restrict__ gsrc,
+                                                    int32_t* __restrict__ gdst) {
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int g = find_instance(eoff, G, e);
+    const int64_t base = voff[g];
+    const int64_t size = voff[g + 1] - base;
+    const int u = src[e], v = dst[e];
+    const bool ok = (unsigned)u < (uint64_t)size && (unsigned)v < (uint64_t)size;
+    gsrc[e] = ok ? (int)(base + u) : -1;
+    gdst[e] = ok ? (int)(base + v) : -1;
+  }
+}
+
+__global__ void cc_status(const CcCtl* ctl, const int32_t* w, int max_rounds, int G,
+                          int32_t* status) {
+  int st = PJ_OK;
+  if (ctl->err & kErrRange) st = PJ_EINVAL;
+  else if (ctl->rounds >= max_rounds && w[max_rounds] != 0) st = PJ_ENOCONV;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x)
+    status[g] = st;
+}
+
+inline int grid_for(int64_t n, int block, int cap) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+// Shiloach and Vishkin bound the rounds by floor(log_{3/2} n) + 2; the guard
+// allows four times that before reporting non-convergence.
+inline int round_guard(int64_t n) {
+  const double lg = n > 1 ? std::floor(std::log((double)n) / std::log(1.5)) : 0.0;
+  return 4 * ((int)lg + 2);
+}
+
+struct CcBuffers {
+  CcCtl* ctl = nullptr;
+  int32_t* NS = nullptr;
+  int32_t* Q = nullptr;
+  int32_t* w = nullptr;
+  int32_t* gsrc = nullptr;
+  int32_t* gdst = nullptr;
+  int32_t* status_tmp = nullptr;
+};
+
+size_t cc_carve(int64_t n, int64_t m, int64_t G, bool batched, bool want_status, int wlen,
+                Workspace* ws, CcBuffers* b) {
+  size_t bytes = 0;
+  auto take = [&](auto*& ptr, size_t count) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(ptr)>>;
+    bytes += ws_bytes(count, sizeof(T));
+    if (ws) ptr = ws->take<T>(count);
+  };
+  take(b->ctl, 1);
+  take(b->NS, (size_t)std::max<int64_t>(n, 1));
+  take(b->Q, (size_t)std::max<int64_t>(n, 1));
+  take(b->w, (size_t)wlen);
+  if (batched) {
+    take(b->gsrc, (size_t)std::max<int64_t>(m, 1));
+    take(b->gdst, (size_t)std::max<int64_t>(m, 1));
+  }
+  if (want_status) take(b->status_tmp, (size_t)std::max<int64_t>(G, 1));
+  return bytes;
+}
+
+int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const int64_t* d_voff,
+            const int64_t* d_eoff, int64_t G, int32_t* label, const pj_opts* user,
+            hipStream_t stream) {
+  const bool batched = d_voff != nullptr;
+  if (!batched) G = 1;
+  if (n < 0 || m < 0 || G < 0 || n >= INT32_MAX || m >= (int64_t(1) << 40)) return PJ_EINVAL;
+  if (n > 0 && !label) return PJ_EINVAL;
+  if (m > 0 && (!src || !dst)) return PJ_EINVAL;
+  if (m > 0 && ((const void*)label == (const void*)src || (const void*)label == (const void*)dst))
+    return PJ_EINVAL;
+  if (m > 0 && n == 0) return PJ_EINVAL;
+  pj_opts o = resolved_opts(user);
+  pj_stats* st = user ? user->stats : nullptr;
+  if (st) *st = pj_stats{};
+  const bool want_status = o.validate && !o.d_status;
+  if (n == 0 && !o.d_status) return PJ_OK;
+
+  const int max_rounds = round_guard(n);
+  const int wlen = max_rounds + 2;
+  CcBuffers b;
+  const size_t need = cc_carve(n, m, G, batched, want_status, wlen, nullptr, &b);
+  Workspace ws;
+  PJ_TRY(workspace_acquire(ws, need, &o, stream));
+  cc_carve(n, m, G, batched, want_status, wlen, &ws, &b);
+  int32_t* status = o.d_status ? o.d_status : b.status_tmp;
+
+  PhaseTimer tm;
+  PJ_TRY(tm.begin(st != nullptr, stream));
+
+  const int ni = (int)n;
+  const int cus = device_info().cus;
+  const int gcap = cus * 16;
+  const int gv = grid_for(n, 256, gcap);
+  const int ge = grid_for((m + 3) / 4, 256, gcap);
+  int32_t* D = label;
+
+  const int32_t* es = src;
+  const int32_t* ed = dst;
+  if (batched && m > 0) {
+    hipLaunchKernelGGL(cc_globalise, dim3(grid_for(m, 256, gcap)), dim3(256), 0, stream, src, dst,
+                       d_voff, d_eoff, (int)G, m, b.gsrc, b.gdst);
+    es = b.gsrc;
+    ed = b.gdst;
+  }
+  hipLaunchKernelGGL(sv_init, dim3(gv), dim3(256), 0, stream, D, b.NS, b.Q, ni, b.w, wlen, b.ctl);
+  PJ_HIP(hipGetLastError());
+  tm.mark("sv0_init");
+
+  // host-visible copy of the change flag, one pinned word per host thread
+  static thread_local int32_t* hflag = nullptr;
+  if (!hflag) PJ_HIP(hipHostMalloc((void**)&hflag, sizeof(int32_t), hipHostMallocDefault));
+  int rounds = 0;
+  bool done = n == 0;
+  int result = PJ_OK;
+  while (!done) {
+    const int chunk = std::min(o.rounds_per_check, max_rounds - rounds);
+    for (int c = 0; c < chunk; ++c) {
+      const int s = ++rounds;
+      hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
+      hipLaunchKernelGGL(sv_mark, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, b.w, s, b.ctl);
+      if (m > 0) {
+        hipLaunchKernelGGL(sv_hook, dim3(ge), dim3(256), 0, stream, es, ed, m, D, b.NS, b.Q, ni,
+                           b.w, s, b.ctl);
+        hipLaunchKernelGGL(sv_stagnant, dim3(ge), dim3(256), 0, stream, es, ed, m, D, b.NS, b.Q,
+                           ni, b.w, s);
+      }
+      hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
+    }
+    PJ_HIP(hipGetLastError());
+    PJ_HIP(hipMemcpyAsync(hflag, b.w + rounds, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+    PJ_HIP(hipStreamSynchronize(stream));
+    if (*hflag == 0) done = true;
+    else if (rounds >= max_rounds) done = true;
+  }
+  tm.mark("sv_rounds");
+
+  if (n > 0) {
+    hipLaunchKernelGGL(canon_init, dim3(gv), dim3(256), 0, stream, b.NS, ni);
+    hipLaunchKernelGGL(canon_min, dim3(grid_for(n, 256 * kCanonPerThread, gcap)), dim3(256), 0,
+                       stream, D, b.NS, ni);
+    if (batched)
+      hipLaunchKernelGGL(canon_label<true>, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, d_voff,
+                         (int)G);
+    else
+      hipLaunchKernelGGL(canon_label<false>, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, d_voff,
+                         (int)G);
+    PJ_HIP(hipGetLastError());
+    tm.mark("canonicalise");
+  }
+  if (status && G > 0) {
+    hipLaunchKernelGGL(cc_status, dim3(grid_for(G, 256, 1024)), dim3(256), 0, stream, b.ctl, b.w,
+                       max_rounds, (int)G, status);
+    PJ_HIP(hipGetLastError());
+  }
+  if (want_status && G > 0) {
+    int32_t hs = 0;
+    PJ_HIP(hipMemcpyAsync(&hs, status, sizeof hs, hipMemcpyDeviceToHost, stream));
+    PJ_HIP(hipStreamSynchronize(stream));
+    result = hs;
+  }
+  if (st) {
+    PJ_TRY(tm.finish(st));
+    st->algo = PJ_ALGO_SV;
+    CcCtl hc{};
+    PJ_HIP(hipMemcpyAsync(&hc, b.ctl, sizeof hc, hipMemcpyDeviceToHost, stream));
+    PJ_HIP(hipStreamSynchronize(stream));
+    st->rounds = hc.rounds;
+    st->level_nodes[0] = n;
+    st->status = result;
+  }
+  PJ_TRY(workspace_release(ws));
+  return result;
+}
+
+}  // namespace
+
+size_t cc_workspace(int64_t n, int64_t m, int64_t G, const pj_opts* user, bool batched) {
+  pj_opts o = resolved_opts(user);
+  CcBuffers b;
+  return cc_carve(n, m, G, batched, o.validate && !o.d_status, round_guard(n) + 2, nullptr, &b);
+}
+
+}  // namespace pj
+
+extern "C" {
+
+int pj_connected_components_ex(const int32_t* src, const int32_t* dst, int64_t n, int64_t m,
+                               int32_t* label, const pj_opts* opts, pj_stream_t stream) {
+  return pj::cc_impl(src, dst, n, m, nullptr, nullptr, 1, label, opts, (hipStream_t)stream);
+}
+
+int pj_connected_components(const int32_t* src, const int32_t* dst, int64_t n, int64_t m,
+                            int32_t* label, pj_stream_t stream) {
+  return pj_connected_components_ex(src, dst, n, m, label, nullptr, stream);
+}
+
+int pj_connected_components_batched_ex(const int32_t* src, const int32_t* dst,
+                                       const int64_t* vtx_off, const int64_t* edge_off,
+                                       int64_t G, int32_t* label, const pj_opts* opts,
+                                       pj_stream_t stream) {
+  if (!vtx_off || !edge_off || G < 0) return PJ_EINVAL;
+  if (G == 0) return PJ_OK;
+  hipStream_t s = (hipStream_t)stream;
+  int64_t n = 0, m = 0;
+  const int64_t* hv = opts ? opts->h_offsets : nullptr;
+  const int64_t* he = opts ? opts->h_edge_offsets : nullptr;
+  if (hv && he) {
+    n = hv[G];
+    m = he[G];
+  } else {
+    int64_t tmp[2] = {0, 0};
+    if (hipMemcpyAsync(&tmp[0], vtx_off + G, sizeof(int64_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(&tmp[1], edge_off + G, sizeof(int64_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+      return PJ_EHIP;
+    n = tmp[0];
+    m = tmp[1];
+  }
+  return pj::cc_impl(src, dst, n, m, vtx_off, edge_off, G, label, opts, s);
+}
+
+int pj_connected_components_batched(const int32_t* src, const int32_t* dst,
+                                    const int64_t* vtx_off, const int64_t* edge_off, int64_t G,
+                                    int32_t* label, pj_stream_t stream) {
+  return pj_connected_components_batched_ex(src, dst, vtx_off, edge_off, G, label, nullptr,
+                                            stream);
+}
+
+size_t pj_cc_workspace_bytes(int64_t n, int64_t m, int64_t G, const pj_opts* opts) {
+  if (n < 0 || m < 0 || G < 1) return 0;
+  return pj::cc_workspace(n, m, G, opts, G > 1);
+}
+
+}  // extern "C"

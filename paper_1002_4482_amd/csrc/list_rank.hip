@@ -1,0 +1,1188 @@
+// List ranking on gfx950: Wyllie pointer jumping and the random-splitter
+// (sparse ruling set) method with recursive ranking of the splitter list.
+//
+// One code path serves a single list and a batch of lists: a single list is
+// a batch with L = 1.  Global node ids run over the concatenation; the
+// successors of level 0 are local to their list.
+//
+// Ruling set, per level l (Section 3.2, "Parallel Random Splitter"):
+//   * splitters: one node per block of 2^log2B consecutive ids, at an offset
+//     drawn by a counter-based hash (so "is y a splitter" is arithmetic, with
+//     no mark array), plus one virtual splitter per list standing at its head;
+//   * walk (the paper's RS3): persistent lanes take splitters from a work
+//     counter and follow successors until the next splitter or the tail,
+//     writing (sublist id, weight before the node) per node and
+//     (next splitter, sublist weight) per splitter.  A walk longer than
+//     max_walk nodes is cut and the cut node becomes a new splitter, which
+//     bounds every loop even on malformed input;
+//   * the splitter lists (one per input list, head = its virtual splitter)
+//     form level l+1, weighted by sublist length, and are ranked the same way
+//     (the recursion replacing the paper's single-block RS4) until a level is
+//     small enough for one workgroup, which ranks it in LDS by pointer
+//     jumping (the paper's single-kernel Wyllie);
+//   * expand (the paper's RS5): rank[x] = rank of its splitter + its weight
+//     offset, a coalesced pass per level.
+// The rank counted here is the distance from the head; the paper's RS5
+// subtracts from the splitter rank because it counts toward the tail.
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+#include "pj_internal.hpp"
+
+namespace pj {
+namespace {
+
+constexpr int kMaxCutoff = 8192;
+constexpr int kBaseThreads = 1024;
+constexpr int kPerThread = kMaxCutoff / kBaseThreads;
+
+struct LevelCtl {
+  int32_t n;     // nodes at this level (level 0: written by init)
+  int32_t r;     // static splitters of this level (written by its walk)
+  int32_t dyn;   // cut points requested at this level (may exceed the cap)
+  int32_t work;  // work counter of the persistent walk
+};
+
+struct LrCtl {
+  LevelCtl lv[PJ_MAX_LEVELS + 2];
+  int32_t err;
+  int32_t pad;
+  unsigned long long base_total;  // total weight seen by the base ranking
+};
+
+// Node count of level `level` >= 1: static + virtual + granted cut points of
+// the level below.
+__device__ __forceinline__ int level_nodes(const LrCtl* ctl, int level, int L, int cap_prev) {
+  if (level == 0) return ctl->lv[0].n;
+  const LevelCtl& p = ctl->lv[level - 1];
+  return p.r + L + min(p.dyn, cap_prev);
+}
+
+__device__ __forceinline__ uint32_t splitter_offset(uint32_t block, uint32_t seed, uint32_t bsize) {
+  uint32_t h = mix32(block * 0x9E3779B9u ^ seed);
+  return (uint32_t)(((uint64_t)h * bsize) >> 32);
+}
+
+// Is id y the static splitter of its block?
+__device__ __forceinline__ bool is_static(int y, int N, int log2B, uint32_t seed) {
+  int b = y >> log2B;
+  int start = b << log2B;
+  int bsize = min(1 << log2B, N - start);
+  return (uint32_t)(y - start) == splitter_offset((uint32_t)b, seed, (uint32_t)bsize);
+}
+
+__device__ __forceinline__ void store_pair(int2* p, int a, int b) { *p = make_int2(a, b); }
+
+// ------------------------------------------------------------------ init
+__global__ void lr_init(LrCtl* ctl, int n0, unsigned long long* lsum, int32_t* ltails,
+                        int32_t* lerr, int L, int64_t* off_single) {
+  int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  int stride = gridDim.x * blockDim.x;
+  int32_t* c = reinterpret_cast<int32_t*>(ctl);
+  for (int i = tid; i < (int)(sizeof(LrCtl) / 4); i += stride) c[i] = 0;
+  for (int i = tid; i < L; i += stride) {
+    lsum[i] = 0ull;
+    ltails[i] = 0;
+    lerr[i] = 0;
+  }
+  if (tid == 0) {
+    ctl->lv[0].n = n0;
+    if (off_single) {
+      off_single[0] = 0;
+      off_single[1] = n0;
+    }
+  }
+}
+
+// ------------------------------------------------------------- head find
+// Head of each list by the index-sum identity: the nodes with a predecessor
+// are exactly the non-tail successors, so
+//   head = size(size-1)/2 - sum of non-tail successors.
+// The same coalesced pass counts tails and flags out-of-range successors.
+__global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restrict__ succ, int n,
+                                                          unsigned long long* lsum,
+                                                          int32_t* ltails, int32_t* lerr) {
+  unsigned long long acc = 0;
+  int tails = 0, bad = 0;
+  const int tid = blockIdx.x * blockDim.x + threadIdx.x;
+  const int stride = gridDim.x * blockDim.x;
+  const int n4 = (reinterpret_cast<uintptr_t>(succ) & 15) == 0 ? (n >> 2) : 0;
+  const int4* s4 = reinterpret_cast<const int4*>(succ);
+  for (int q = tid; q < n4; q += stride) {
+    const int4 v = s4[q];
+    int i = q << 2;
+    int vs[4] = {v.x, v.y, v.z, v.w};
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      int s = vs[t];
+      bool tail = (s == -1) | (s == i + t);
+      bool range = (unsigned)s < (unsigned)n;
+      tails += tail;
+      bad |= (!tail & !range);
+      acc += (!tail & range) ? (unsigned long long)s : 0ull;
+    }
+  }
+  for (int i = (n4 << 2) + tid; i < n; i += stride) {
+    int s = succ[i];
+    bool tail = (s == -1) | (s == i);
+    bool range = (unsigned)s < (unsigned)n;
+    tails += tail;
+    bad |= (!tail & !range);
+    acc += (!tail & range) ? (unsigned long long)s : 0ull;
+  }
+  acc = wave_sum(acc);
+  tails = wave_sum(tails);
+  bad = wave_sum(bad);
+  if (lane_id() == 0) {
+    if (acc) atomicAdd(lsum, acc);
+    if (tails) atomicAdd(ltails, tails);
+    if (bad) atomicOr(lerr, kErrRange);
+  }
+}
+
+// Batched form: each wave owns chunks of 64*kChunk consecutive positions and
+// tracks the owning list while it advances.
+constexpr int kHfChunk = 16;
+__global__ void __launch_bounds__(256) lr_headfind_batched(const int32_t* __restrict__ succ,
+                                                           const int64_t* __restrict__ off, int L,
+                                                           int n, unsigned long long* lsum,
+                                                           int32_t* ltails, int32_t* lerr) {
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nwaves = (gridDim.x * blockDim.x) / kWave;
+  const int lane = lane_id();
+  const int chunk = kWave * kHfChunk;
+  for (int64_t c0 = (int64_t)wave * chunk; c0 < n; c0 += (int64_t)nwaves * chunk) {
+    int l = find_instance(off, L, c0);
+    int64_t lend = off[l + 1];
+    int64_t lbase = off[l];
+    unsigned long long acc = 0;
+    int tails = 0;
+    for (int t = 0; t < kHfChunk; ++t) {
+      int64_t g = c0 + t * kWave + lane;
+      if (g >= n) break;
+      if (g >= lend) {  // moved into a later list: flush
+        if (acc) atomicAdd(&lsum[l], acc);
+        if (tails) atomicAdd(&ltails[l], tails);
+        acc = 0;
+        tails = 0;
+        while (off[l + 1] <= g) ++l;
+        lbase = off[l];
+        lend = off[l + 1];
+      }
+      int s = succ[g];
+      int x = (int)(g - lbase);
+      int size = (int)(lend - lbase);
+      bool tail = (s == -1) | (s == x);
+      bool range = (unsigned)s < (unsigned)size;
+      tails += tail;
+      if (!tail & !range) atomicOr(&lerr[l], kErrRange);
+      acc += (!tail & range) ? (unsigned long long)s : 0ull;
+    }
+    // wave-combine when the whole wave ended in one list
+    int l0 = __shfl(l, 0);
+    if (__ballot(l != l0) == 0) {
+      acc = wave_sum(acc);
+      tails = wave_sum(tails);
+      if (lane == 0) {
+        if (acc) atomicAdd(&lsum[l], acc);
+        if (tails) atomicAdd(&ltails[l], tails);
+      }
+    } else {
+      if (acc) atomicAdd(&lsum[l], acc);
+      if (tails) atomicAdd(&ltails[l], tails);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ walk
+struct WalkArgs {
+  const int32_t* succ0;              // level 0: local successors
+  const int2* link_in;               // level >= 1: {next, weight} per node
+  const int64_t* off;                // level 0: list offsets (L+1)
+  const unsigned long long* lsum;    // level 0: head-find sums
+  const int32_t* ltails;             // level 0: tail counts
+  int32_t* lerr;                     // per-list error bits
+  int2* state;                       // {sublist id, weight before node} per node
+  int2* link_out;                    // {next splitter, sublist weight} per splitter
+  LrCtl* ctl;
+  int L;
+  int level;
+  int log2B;
+  int max_walk;
+  int cap;       // cut points this level may create
+  int cap_prev;  // cut points the level below could create
+  uint32_t seed;
+};
+
+template <bool kLevel0, bool kBatched>
+__global__ void __launch_bounds__(256) lr_walk(WalkArgs a) {
+  LrCtl* ctl = a.ctl;
+  const int N = level_nodes(ctl, a.level, a.L, a.cap_prev);
+  const int log2B = a.log2B;
+  const int r = (int)(((int64_t)N + (1 << log2B) - 1) >> log2B);
+  const int head_base = kLevel0 ? 0 : ctl->lv[a.level - 1].r;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->lv[a.level].r = r;
+  const int items = r + a.L;
+  int* work = &ctl->lv[a.level].work;
+  int* dyn = &ctl->lv[a.level].dyn;
+  const uint32_t seed = a.seed;
+
+  int sid = -1;       // sublist being walked, -1 = idle
+  int x = 0;          // current node
+  int k = 0;          // weight of the sublist before x
+  int steps = 0;
+  int64_t base = 0;   // level 0: first id of the lane's list
+  int size = N;       // level 0: size of the lane's list
+  int lid = 0;        // level 0: list index
+  bool retired = false;
+  int errbits = 0;
+
+  while (true) {
+    const bool need = (sid < 0) & !retired;
+    const uint64_t needm = __ballot(need);
+    if (needm) {
+      const int leader = __builtin_ctzll(needm);
+      int first = 0;
+      if (lane_id() == leader) first = atomicAdd(work, __popcll(needm));
+      first = __shfl(first, leader);
+      if (need) {
+        const int item = first + lanes_below(needm);
+        if (item >= items) {
+          retired = true;
+        } else if (item < r) {  // static splitter
+          const int start = item << log2B;
+          const int bsize = min(1 << log2B, N - start);
+          x = start + (int)splitter_offset((uint32_t)item, seed, (uint32_t)bsize);
+          if (kLevel0 && kBatched) {
+            lid = find_instance(a.off, a.L, x);
+            base = a.off[lid];
+            size = (int)(a.off[lid + 1] - base);
+          }
+          sid = item;
+          k = 0;
+          steps = 0;
+        } else {  // virtual splitter standing at the head of list l
+          const int l = item - r;
+          int h;
+          bool ok = true;
+          if (kLevel0) {
+            if (kBatched) {
+              base = a.off[l];
+              size = (int)(a.off[l + 1] - base);
+            } else {
+              base = 0;
+              size = N;
+            }
+            lid = l;
+            if (size == 0) {
+              ok = false;  // empty list: a weightless one-node list above
+            } else {
+              const unsigned long long tri =
+                  (unsigned long long)size * (unsigned long long)(size - 1) / 2ull;
+              const long long hl = (long long)(tri - a.lsum[l]);
+              if (a.ltails[l] != 1 || hl < 0 || hl >= size) {
+                atomicOr(&a.lerr[l], a.ltails[l] != 1 ? kErrTails : kErrHead);
+                ok = false;
+              }
+              h = (int)(base + hl);
+            }
+          } else {
+            h = head_base + l;
+            if (h >= N) {
+              errbits |= kErrBase;
+              ok = false;
+            }
+          }
+          if (!ok) {
+            store_pair(&a.link_out[item], -1, 0);
+          } else if (is_static(h, N, log2B, seed)) {
+            store_pair(&a.link_out[item], h >> log2B, 0);
+          } else {
+            x = h;
+            sid = item;
+            k = 0;
+            steps = 0;
+          }
+        }
+      }
+    }
+    if (__ballot(!retired) == 0) break;
+    if (sid >= 0) {
+      int y, w;
+      bool tail;
+      if (kLevel0) {
+        const int s = a.succ0[x];
+        const int xl = (int)(x - base);
+        tail = (s == -1) | (s == xl);
+        if (!tail && (unsigned)s >= (unsigned)size) {
+          atomicOr(&a.lerr[lid], kErrRange);
+          tail = true;
+        }
+        y = (int)(base + s);
+        w = 1;
+      } else {
+        const int2 in = a.link_in[x];
+        tail = in.x == -1;
+        if (!tail && (unsigned)in.x >= (unsigned)N) {
+          errbits |= kErrBase;
+          tail = true;
+        }
+        y = in.x;
+        w = in.y;
+      }
+      store_pair(&a.state[x], sid, k);
+      k += w;
+      if (tail) {
+        store_pair(&a.link_out[sid], -1, k);
+        sid = -1;
+      } else if (is_static(y, N, log2B, seed)) {
+        store_pair(&a.link_out[sid], y >> log2B, k);
+        sid = -1;
+      } else if (++steps >= a.max_walk) {
+        const int t = atomicAdd(dyn, 1);
+        if (t >= a.cap) {
+          errbits |= kErrOverflow;
+          store_pair(&a.link_out[sid], -1, k);
+          sid = -1;
+        } else {
+          const int nid = r + a.L + t;
+          store_pair(&a.link_out[sid], nid, k);
+          sid = nid;
+          k = 0;
+          steps = 0;
+          x = y;
+        }
+      } else {
+        x = y;
+      }
+    }
+  }
+  if (errbits) atomicOr(&ctl->err, errbits);
+}
+
+// ------------------------------------------------------------ base: LDS
+// Ranks a weighted forest of at most kMaxCutoff nodes in one workgroup:
+// predecessor links are built in LDS, then pointer jumping along them sums
+// the weights of all earlier nodes (exclusive prefix from each head).  The
+// heads must be exactly the ids head_base .. head_base + L - 1.
+__global__ void __launch_bounds__(kBaseThreads) lr_base_lds(const int2* __restrict__ link,
+                                                            int32_t* __restrict__ srank,
+                                                            LrCtl* ctl, int level, int L,
+                                                            int cap_prev) {
+  __shared__ int lnk[kMaxCutoff];
+  __shared__ int pre[kMaxCutoff];
+  __shared__ int nheads;
+  __shared__ int bad;
+  __shared__ unsigned long long total;
+  const int N = level_nodes(ctl, level, L, cap_prev);
+  const int head_base = ctl->lv[level - 1].r;
+  const int tid = threadIdx.x;
+  if (tid == 0) {
+    nheads = 0;
+    bad = 0;
+    total = 0ull;
+  }
+  if (N > kMaxCutoff) {
+    if (tid == 0) atomicOr(&ctl->err, kErrBase);
+    return;
+  }
+  for (int j = tid; j < N; j += kBaseThreads) lnk[j] = -1;
+  __syncthreads();
+  unsigned long long mytotal = 0;
+  for (int j = tid; j < N; j += kBaseThreads) {
+    const int2 in = link[j];
+    mytotal += (unsigned)in.y;
+    if (in.x >= 0 && in.x < N) {
+      if (atomicExch(&lnk[in.x], j) != -1) bad = 1;
+    } else if (in.x != -1) {
+      bad = 1;
+    }
+  }
+  __syncthreads();
+  int myheads = 0;
+  for (int j = tid; j < N; j += kBaseThreads) {
+    const int p = lnk[j];
+    pre[j] = p >= 0 ? link[p].y : 0;
+    if (p < 0) {
+      ++myheads;
+      if (j < head_base || j >= head_base + L) bad = 1;
+    }
+  }
+  if (myheads) atomicAdd(&nheads, myheads);
+  mytotal = wave_sum(mytotal);
+  if (lane_id() == 0 && mytotal) atomicAdd(&total, mytotal);
+  __syncthreads();
+  int rounds = 0;
+  while ((1 << rounds) < N) ++rounds;
+  int pa[kPerThread], la[kPerThread];
+  for (int it = 0; it < rounds; ++it) {
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = tid + t * kBaseThreads;
+      la[t] = -1;
+      pa[t] = 0;
+      if (j < N) {
+        const int p = lnk[j];
+        if (p >= 0) {
+          pa[t] = pre[p];
+          la[t] = lnk[p];
+        } else {
+          la[t] = -2;
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = tid + t * kBaseThreads;
+      if (j < N && la[t] != -2) {
+        pre[j] += pa[t];
+        lnk[j] = la[t];
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < N; j += kBaseThreads) {
+    if (lnk[j] != -1) bad = 1;
+    srank[j] = pre[j];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    if (bad || nheads != L) atomicOr(&ctl->err, kErrBase);
+    ctl->base_total = total;
+  }
+}
+
+// ---------------------------------------------------- base: device-wide
+// The same predecessor pointer jumping for forests too large for one
+// workgroup, one launch per round; (prefix, link) pairs are packed into one
+// 64-bit word so a gather reads a consistent pair.
+__device__ __forceinline__ unsigned long long pack_pl(int prefix, int lnk) {
+  return ((unsigned long long)(unsigned)prefix << 32) | (unsigned)lnk;
+}
+
+__global__ void wide_clear(int32_t* lnk, const LrCtl* ctl, int level, int L, int cap_prev) {
+  const int N = level_nodes(ctl, level, L, cap_prev);
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x)
+    lnk[j] = -1;
+}
+
+__global__ void wide_pred(const int2* __restrict__ link, int32_t* lnk, LrCtl* ctl, int level,
+                          int L, int cap_prev) {
+  const int N = level_nodes(ctl, level, L, cap_prev);
+  int bad = 0;
+  unsigned long long tot = 0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    const int2 in = link[j];
+    tot += (unsigned)in.y;
+    if (in.x >= 0 && in.x < N) {
+      if (atomicExch(&lnk[in.x], j) != -1) bad = 1;
+    } else if (in.x != -1) {
+      bad = 1;
+    }
+  }
+  tot = wave_sum(tot);
+  if (lane_id() == 0 && tot) atomicAdd(&ctl->base_total, tot);
+  if (bad) atomicOr(&ctl->err, kErrBase);
+}
+
+__global__ void wide_init(const int2* __restrict__ link, const int32_t* __restrict__ lnk,
+                          unsigned long long* pl, LrCtl* ctl, int level, int L, int cap_prev) {
+  const int N = level_nodes(ctl, level, L, cap_prev);
+  const int head_base = ctl->lv[level - 1].r;
+  int bad = 0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    const int p = lnk[j];
+    if (p < 0 && (j < head_base || j >= head_base + L)) bad = 1;
+    pl[j] = pack_pl(p >= 0 ? link[p].y : 0, p);
+  }
+  if (bad) atomicOr(&ctl->err, kErrBase);
+}
+
+__global__ void wide_jump(unsigned long long* pl, const LrCtl* ctl, int level, int L,
+                          int cap_prev) {
+  const int N = level_nodes(ctl, level, L, cap_prev);
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    const unsigned long long v = pl[j];
+    const int p = (int)(unsigned)v;
+    if (p < 0) continue;
+    const unsigned long long q = pl[p];
+    const int pre = (int)(v >> 32) + (int)(q >> 32);
+    pl[j] = pack_pl(pre, (int)(unsigned)q);
+  }
+}
+
+__global__ void wide_final(const unsigned long long* __restrict__ pl, int32_t* srank, LrCtl* ctl,
+                           int level, int L, int cap_prev) {
+  const int N = level_nodes(ctl, level, L, cap_prev);
+  int bad = 0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    const unsigned long long v = pl[j];
+    if ((int)(unsigned)v != -1) bad = 1;
+    srank[j] = (int)(v >> 32);
+  }
+  if (bad) atomicOr(&ctl->err, kErrBase);
+}
+
+// ---------------------------------------------------------------- expand
+// rank of node x = rank of its splitter + weight before x in its sublist.
+__global__ void __launch_bounds__(256) lr_expand(const int2* __restrict__ state,
+                                                 const int32_t* __restrict__ srank_up,
+                                                 int32_t* __restrict__ out, LrCtl* ctl, int level,
+                                                 int L, int cap_prev, int cap_here) {
+  const int N = level_nodes(ctl, level, L, cap_prev);
+  const int Nup = level_nodes(ctl, level + 1, L, cap_here);
+  int bad = 0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += gridDim.x * blockDim.x) {
+    const int2 s = state[j];
+    int v = 0;
+    if ((unsigned)s.x < (unsigned)Nup) v = srank_up[s.x] + s.y;
+    else bad = 1;
+    out[j] = v;
+  }
+  if (bad) atomicOr(&ctl->err, kErrTotal);
+}
+
+// Level 0: write the output ranks (from the head, or to the tail).
+template <bool kBatched, bool kToTail>
+__global__ void __launch_bounds__(256) lr_expand0(const int2* __restrict__ state,
+                                                  const int32_t* __restrict__ srank_up,
+                                                  int32_t* __restrict__ rank,
+                                                  const int64_t* __restrict__ off, LrCtl* ctl,
+                                                  int L, int cap_here) {
+  const int N = ctl->lv[0].n;
+  const int Nup = level_nodes(ctl, 1, L, cap_here);
+  int bad = 0;
+  const int stride = gridDim.x * blockDim.x;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += stride) {
+    const int2 s = state[j];
+    int v = 0;
+    if ((unsigned)s.x < (unsigned)Nup) v = srank_up[s.x] + s.y;
+    else bad = 1;
+    if (kToTail) {
+      int size = N;
+      if (kBatched) {
+        const int l = find_instance(off, L, j);
+        size = (int)(off[l + 1] - off[l]);
+      }
+      v = size - 1 - v;
+    }
+    __builtin_nontemporal_store(v, &rank[j]);
+  }
+  if (bad) atomicOr(&ctl->err, kErrTotal);
+}
+
+// --------------------------------------------------------------- Wyllie
+// Pointer jumping (Section 3.1) on packed (distance to tail, next) pairs:
+// one 64-bit read of the node's own pair, one 64-bit gather of its next's
+// pair, one 64-bit write.  Updating in place is safe: a gather that sees a
+// pair already advanced in this round still holds a consistent
+// (distance, next) relation, only a longer jump.
+__device__ __forceinline__ unsigned long long pack_dn(int dist, int next) {
+  return ((unsigned long long)(unsigned)dist << 32) | (unsigned)next;
+}
+
+template <bool kBatched>
+__global__ void __launch_bounds__(256) wy_init(const int32_t* __restrict__ succ,
+                                               const int64_t* __restrict__ off, int L, int n,
+                                               unsigned long long* __restrict__ pair,
+                                               int32_t* lerr) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
+    int64_t base = 0;
+    int size = n, l = 0;
+    if (kBatched) {
+      l = find_instance(off, L, g);
+      base = off[l];
+      size = (int)(off[l + 1] - base);
+    }
+    const int s = succ[g];
+    const int xl = (int)(g - base);
+    bool tail = (s == -1) | (s == xl);
+    if (!tail && (unsigned)s >= (unsigned)size) {
+      atomicOr(&lerr[l], kErrRange);
+      tail = true;
+    }
+    pair[g] = tail ? pack_dn(0, -1) : pack_dn(1, (int)(base + s));
+  }
+}
+
+__global__ void __launch_bounds__(256) wy_jump(unsigned long long* __restrict__ pair, int n) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
+    const unsigned long long v = pair[g];
+    const int nx = (int)(unsigned)v;
+    if (nx < 0) continue;
+    const unsigned long long q = pair[nx];
+    pair[g] = pack_dn((int)(v >> 32) + (int)(q >> 32), (int)(unsigned)q);
+  }
+}
+
+template <bool kBatched, bool kToTail>
+__global__ void __launch_bounds__(256) wy_final(const unsigned long long* __restrict__ pair,
+                                                const int64_t* __restrict__ off, int L, int n,
+                                                int32_t* __restrict__ rank, int32_t* lerr) {
+  const int stride = gridDim.x * blockDim.x;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
+    const unsigned long long v = pair[g];
+    const int dist = (int)(v >> 32);
+    int l = 0, size = n;
+    if (kBatched) {
+      l = find_instance(off, L, g);
+      size = (int)(off[l + 1] - off[l]);
+    }
+    if ((int)(unsigned)v != -1) atomicOr(&lerr[l], kErrBase);
+    rank[g] = kToTail ? dist : size - 1 - dist;
+  }
+}
+
+// ------------------------------------------------------- small one-group
+// A whole batch of at most kMaxCutoff nodes ranked by one workgroup:
+// predecessor links in LDS, pointer jumping along them with unit weights.
+__global__ void __launch_bounds__(kBaseThreads) lr_small(const int32_t* __restrict__ succ,
+                                                         const int64_t* __restrict__ off, int L,
+                                                         int n, int32_t* __restrict__ rank,
+                                                         int to_tail, int32_t* ltails,
+                                                         int32_t* lerr) {
+  __shared__ int lnk[kMaxCutoff];
+  __shared__ int pre[kMaxCutoff];
+  const int tid = threadIdx.x;
+  for (int j = tid; j < n; j += kBaseThreads) lnk[j] = -1;
+  __syncthreads();
+  for (int j = tid; j < n; j += kBaseThreads) {
+    const int l = find_instance(off, L, j);
+    const int base = (int)off[l];
+    const int size = (int)(off[l + 1] - base);
+    const int s = succ[j];
+    const bool tail = (s == -1) | (s == j - base);
+    if (tail) {
+      atomicAdd(&ltails[l], 1);
+    } else if ((unsigned)s >= (unsigned)size) {
+      atomicOr(&lerr[l], kErrRange);
+    } else if (atomicExch(&lnk[base + s], j) != -1) {
+      atomicOr(&lerr[l], kErrBase);
+    }
+  }
+  __syncthreads();
+  for (int j = tid; j < n; j += kBaseThreads) pre[j] = lnk[j] >= 0 ? 1 : 0;
+  __syncthreads();
+  int rounds = 0;
+  while ((1 << rounds) < n) ++rounds;
+  int pa[kPerThread], la[kPerThread];
+  for (int it = 0; it < rounds; ++it) {
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = tid + t * kBaseThreads;
+      la[t] = -2;
+      pa[t] = 0;
+      if (j < n) {
+        const int p = lnk[j];
+        if (p >= 0) {
+          pa[t] = pre[p];
+          la[t] = lnk[p];
+        }
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = tid + t * kBaseThreads;
+      if (j < n && la[t] != -2) {
+        pre[j] += pa[t];
+        lnk[j] = la[t];
+      }
+    }
+    __syncthreads();
+  }
+  for (int j = tid; j < n; j += kBaseThreads) {
+    const int l = find_instance(off, L, j);
+    const int size = (int)(off[l + 1] - off[l]);
+    if (lnk[j] != -1) atomicOr(&lerr[l], kErrBase);
+    const int v = pre[j];
+    rank[j] = to_tail ? size - 1 - v : v;
+  }
+}
+
+// ------------------------------------------------------------ full check
+// Complete check of the output (validate = 1): per list, ranks are a
+// permutation of 0..size-1 and rank[succ[i]] = rank[i] + 1 off the tail.
+__global__ void chk_clear(int32_t* cnt, int n) {
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < n; j += gridDim.x * blockDim.x)
+    cnt[j] = 0;
+}
+
+template <bool kBatched>
+__global__ void chk_count(const int32_t* __restrict__ succ, const int32_t* __restrict__ rank,
+                          const int64_t* __restrict__ off, int L, int n, int to_tail,
+                          int32_t* cnt, int32_t* lerr) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+    int64_t base = 0;
+    int size = n, l = 0;
+    if (kBatched) {
+      l = find_instance(off, L, g);
+      base = off[l];
+      size = (int)(off[l + 1] - base);
+    }
+    int r = rank[g];
+    if (to_tail) r = size - 1 - r;
+    if ((unsigned)r >= (unsigned)size) {
+      atomicOr(&lerr[l], kErrCheck);
+      continue;
+    }
+    atomicAdd(&cnt[base + r], 1);
+    const int s = succ[g];
+    const int xl = (int)(g - base);
+    if (s == -1 || s == xl) continue;
+    if ((unsigned)s >= (unsigned)size) {
+      atomicOr(&lerr[l], kErrCheck);
+      continue;
+    }
+    int rs = rank[base + s];
+    if (to_tail) rs = size - 1 - rs;
+    if (rs != r + 1) atomicOr(&lerr[l], kErrCheck);
+  }
+}
+
+template <bool kBatched>
+__global__ void chk_perm(const int32_t* __restrict__ cnt, const int64_t* __restrict__ off, int L,
+                         int n, int32_t* lerr) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+    if (cnt[g] != 1) {
+      const int l = kBatched ? find_instance(off, L, g) : 0;
+      atomicOr(&lerr[l], kErrCheck);
+    }
+  }
+}
+
+// ---------------------------------------------------------------- status
+__global__ void lr_status(const LrCtl* ctl, const int32_t* lerr, const int32_t* ltails,
+                          const int64_t* off, int L, int n0, int check_total, int check_tails,
+                          int32_t* status) {
+  const bool global_bad = ctl && (ctl->err != 0 ||
+                                  (check_total && ctl->base_total != (unsigned long long)n0));
+  for (int l = blockIdx.x * blockDim.x + threadIdx.x; l < L; l += gridDim.x * blockDim.x) {
+    const int64_t size = off[l + 1] - off[l];
+    bool bad = global_bad || lerr[l] != 0;
+    if (check_tails && size > 0 && ltails[l] != 1) bad = true;
+    status[l] = bad ? PJ_EBADLIST : PJ_OK;
+  }
+}
+
+// ------------------------------------------------------------------ host
+inline int ilog2(int v) {
+  int r = 0;
+  while ((1 << r) < v) ++r;
+  return r;
+}
+
+inline int grid_for(int64_t n, int block, int cap) {
+  int64_t g = (n + block - 1) / block;
+  if (g < 1) g = 1;
+  if (g > cap) g = cap;
+  return (int)g;
+}
+
+struct Plan {
+  int algo = PJ_ALGO_RULING_SET;
+  bool small = false;
+  int levels = 0;          // walk levels
+  int base_kind = 1;       // 1 LDS, 2 device-wide
+  int64_t bound[PJ_MAX_LEVELS + 2] = {};
+  int log2B[PJ_MAX_LEVELS + 1] = {};
+  int cap[PJ_MAX_LEVELS + 1] = {};
+  int wide_rounds = 0;
+  int wy_rounds = 0;
+};
+
+Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o) {
+  Plan p;
+  p.algo = o.algo == PJ_ALGO_WYLLIE ? PJ_ALGO_WYLLIE : PJ_ALGO_RULING_SET;
+  p.bound[0] = n0;
+  if (p.algo == PJ_ALGO_WYLLIE) {
+    p.wy_rounds = ilog2((int)std::max<int64_t>(max_size, 1));
+    return p;
+  }
+  if (n0 <= kMaxCutoff && n0 <= o.cutoff) {
+    p.small = true;
+    return p;
+  }
+  int lv = 0;
+  for (;;) {
+    const int64_t b = p.bound[lv];
+    if (lv > 0) {
+      if (b <= o.cutoff) {
+        p.base_kind = 1;
+        break;
+      }
+      if (lv >= PJ_MAX_LEVELS || b * 4 > p.bound[lv - 1] * 3) {
+        p.base_kind = 2;
+        p.wide_rounds = ilog2((int)b);
+        break;
+      }
+    }
+    const int spacing = lv == 0 ? o.spacing : o.spacing_up;
+    p.log2B[lv] = ilog2(std::max(2, spacing));
+    const int64_t r = (b + (1ll << p.log2B[lv]) - 1) >> p.log2B[lv];
+    p.cap[lv] = (int)(b / o.max_walk + 64);
+    p.bound[lv + 1] = r + L + p.cap[lv];
+    ++lv;
+  }
+  p.levels = lv;
+  return p;
+}
+
+struct Buffers {
+  LrCtl* ctl = nullptr;
+  unsigned long long* lsum = nullptr;
+  int32_t* ltails = nullptr;
+  int32_t* lerr = nullptr;
+  int64_t* off1 = nullptr;            // {0, n} for the single-list call
+  int2* state[PJ_MAX_LEVELS + 1] = {};
+  int2* link[PJ_MAX_LEVELS + 2] = {};  // link[l] = input of level l (l >= 1)
+  int32_t* srank[PJ_MAX_LEVELS + 2] = {};
+  int32_t* wide_lnk = nullptr;
+  unsigned long long* wide_pl = nullptr;
+  unsigned long long* wy_pair = nullptr;
+  int32_t* chk = nullptr;
+  int32_t* status_tmp = nullptr;
+};
+
+// Carve (or, with ws == nullptr, just count) the buffers a plan needs.
+size_t carve(const Plan& p, int64_t L, bool single, bool validate, bool want_status,
+             Workspace* ws, Buffers* b) {
+  size_t bytes = 0;
+  auto take = [&](auto*& ptr, size_t count) {
+    using T = std::remove_pointer_t<std::remove_reference_t<decltype(ptr)>>;
+    bytes += ws_bytes(count, sizeof(T));
+    if (ws) ptr = ws->take<T>(count);
+  };
+  take(b->ctl, 1);
+  take(b->lsum, (size_t)std::max<int64_t>(L, 1));
+  take(b->ltails, (size_t)std::max<int64_t>(L, 1));
+  take(b->lerr, (size_t)std::max<int64_t>(L, 1));
+  if (single) take(b->off1, 2);
+  if (validate) take(b->chk, (size_t)p.bound[0]);
+  if (want_status) take(b->status_tmp, (size_t)std::max<int64_t>(L, 1));
+  if (p.algo == PJ_ALGO_WYLLIE) {
+    take(b->wy_pair, (size_t)p.bound[0]);
+    return bytes;
+  }
+  if (p.small) return bytes;
+  for (int l = 0; l < p.levels; ++l) {
+    take(b->state[l], (size_t)p.bound[l]);
+    take(b->link[l + 1], (size_t)p.bound[l + 1]);
+    take(b->srank[l + 1], (size_t)p.bound[l + 1]);
+  }
+  if (p.base_kind == 2) {
+    take(b->wide_lnk, (size_t)p.bound[p.levels]);
+    take(b->wide_pl, (size_t)p.bound[p.levels]);
+  }
+  return bytes;
+}
+
+int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,
+                   int64_t n_single, int32_t* rank, const pj_opts* user, hipStream_t stream) {
+  const bool single = d_off == nullptr;
+  if (L < 0) return PJ_EINVAL;
+  if (single) L = 1;
+  if (L > INT32_MAX / 2) return PJ_EINVAL;
+  pj_opts o = resolved_opts(user);
+  if (o.spacing > 65536 || o.spacing_up > 65536) return PJ_EINVAL;
+  if (user && user->stats) {
+    *user->stats = pj_stats{};
+    user->stats->status = PJ_OK;
+  }
+
+  // total nodes and the largest list, from the host's view of the offsets
+  int64_t n0 = 0, max_size = 0;
+  std::vector<int64_t> hbuf;
+  if (single) {
+    n0 = n_single;
+    max_size = n0;
+  } else {
+    if (L == 0) return PJ_OK;
+    const int64_t* ho = h_off;
+    if (!ho) {
+      hbuf.resize((size_t)L + 1);
+      PJ_HIP(hipMemcpyAsync(hbuf.data(), d_off, sizeof(int64_t) * (L + 1),
+                            hipMemcpyDeviceToHost, stream));
+      PJ_HIP(hipStreamSynchronize(stream));
+      ho = hbuf.data();
+    }
+    if (ho[0] != 0) return PJ_EINVAL;
+    for (int64_t l = 0; l < L; ++l) {
+      const int64_t s = ho[l + 1] - ho[l];
+      if (s < 0) return PJ_EINVAL;
+      max_size = std::max(max_size, s);
+    }
+    n0 = ho[L];
+  }
+  if (n0 < 0 || n0 >= INT32_MAX) return PJ_EINVAL;
+  if (n0 > 0 && (!succ || !rank)) return PJ_EINVAL;
+  if (n0 > 0 && (const void*)succ == (const void*)rank) return PJ_EINVAL;
+  const bool want_status = o.validate && !o.d_status;
+  if (n0 == 0 && !o.d_status) return PJ_OK;
+
+  Plan p = make_plan(n0, L, max_size, o);
+  Buffers b;
+  const size_t need = carve(p, L, single, o.validate != 0, want_status, nullptr, &b);
+  Workspace ws;
+  PJ_TRY(workspace_acquire(ws, need, &o, stream));
+  carve(p, L, single, o.validate != 0, want_status, &ws, &b);
+  const int64_t* off = single ? b.off1 : d_off;
+  int32_t* status = o.d_status ? o.d_status : b.status_tmp;
+
+  PhaseTimer tm;
+  pj_stats* st = user ? user->stats : nullptr;
+  PJ_TRY(tm.begin(st != nullptr, stream));
+
+  const int n = (int)n0;
+  const int Li = (int)L;
+  const int blk = o.block;
+  const int cus = device_info().cus;
+  const int gcap = cus * 16;
+
+  hipLaunchKernelGGL(lr_init, dim3(grid_for(std::max<int64_t>(L, 64), 256, 1024)), dim3(256), 0,
+                     stream, b.ctl, n, b.lsum, b.ltails, b.lerr, Li, b.off1);
+  PJ_HIP(hipGetLastError());
+  tm.mark("init");
+
+  bool check_total = false, check_tails = false;
+  if (n0 > 0 && p.algo == PJ_ALGO_WYLLIE) {
+    if (o.validate || o.d_status) {
+      if (single)
+        hipLaunchKernelGGL(lr_headfind_single, dim3(grid_for(n / 4 + 1, 256, gcap)), dim3(256),
+                           0, stream, succ, n, b.lsum, b.ltails, b.lerr);
+      else
+        hipLaunchKernelGGL(lr_headfind_batched,
+                           dim3(grid_for(n / (kHfChunk * 4) + 1, 256, gcap)), dim3(256), 0,
+                           stream, succ, off, Li, n, b.lsum, b.ltails, b.lerr);
+      check_tails = true;
+      tm.mark("headfind");
+    }
+    const int g = grid_for(n, blk, gcap);
+    if (single)
+      hipLaunchKernelGGL(wy_init<false>, dim3(g), dim3(blk), 0, stream, succ, off, Li, n,
+                         b.wy_pair, b.lerr);
+    else
+      hipLaunchKernelGGL(wy_init<true>, dim3(g), dim3(blk), 0, stream, succ, off, Li, n,
+                         b.wy_pair, b.lerr);
+    tm.mark("wyllie_init");
+    for (int it = 0; it < p.wy_rounds; ++it)
+      hipLaunchKernelGGL(wy_jump, dim3(g), dim3(blk), 0, stream, b.wy_pair, n);
+    tm.mark("wyllie_jump");
+    if (single) {
+      if (o.to_tail)
+        hipLaunchKernelGGL((wy_final<false, true>), dim3(g), dim3(blk), 0, stream, b.wy_pair, off,
+                           Li, n, rank, b.lerr);
+      else
+        hipLaunchKernelGGL((wy_final<false, false>), dim3(g), dim3(blk), 0, stream, b.wy_pair,
+                           off, Li, n, rank, b.lerr);
+    } else {
+      if (o.to_tail)
+        hipLaunchKernelGGL((wy_final<true, true>), dim3(g), dim3(blk), 0, stream, b.wy_pair, off,
+                           Li, n, rank, b.lerr);
+      else
+        hipLaunchKernelGGL((wy_final<true, false>), dim3(g), dim3(blk), 0, stream, b.wy_pair,
+                           off, Li, n, rank, b.lerr);
+    }
+    tm.mark("wyllie_final");
+  } else if (n0 > 0 && p.small) {
+    hipLaunchKernelGGL(lr_small, dim3(1), dim3(kBaseThreads), 0, stream, succ, off, Li, n, rank,
+                       o.to_tail, b.ltails, b.lerr);
+    check_tails = true;
+    tm.mark("small");
+  } else if (n0 > 0) {
+    // level 0 head find
+    if (single)
+      hipLaunchKernelGGL(lr_headfind_single, dim3(grid_for(n / 4 + 1, 256, gcap)), dim3(256), 0,
+                         stream, succ, n, b.lsum, b.ltails, b.lerr);
+    else
+      hipLaunchKernelGGL(lr_headfind_batched, dim3(grid_for(n / (kHfChunk * 4) + 1, 256, gcap)),
+                         dim3(256), 0, stream, succ, off, Li, n, b.lsum, b.ltails, b.lerr);
+    PJ_HIP(hipGetLastError());
+    tm.mark("headfind");
+    check_total = true;
+    check_tails = true;
+    // walks, level by level
+    for (int lv = 0; lv < p.levels; ++lv) {
+      WalkArgs a{};
+      a.succ0 = succ;
+      a.link_in = b.link[lv];
+      a.off = off;
+      a.lsum = b.lsum;
+      a.ltails = b.ltails;
+      a.lerr = b.lerr;
+      a.state = b.state[lv];
+      a.link_out = b.link[lv + 1];
+      a.ctl = b.ctl;
+      a.L = Li;
+      a.level = lv;
+      a.log2B = p.log2B[lv];
+      a.max_walk = o.max_walk;
+      a.cap = p.cap[lv];
+      a.cap_prev = lv > 0 ? p.cap[lv - 1] : 0;
+      a.seed = level_seed(o.seed, lv);
+      const void* kfn;
+      if (lv == 0)
+        kfn = single ? (const void*)lr_walk<true, false> : (const void*)lr_walk<true, true>;
+      else
+        kfn = (const void*)lr_walk<false, false>;
+      const int64_t items = ((p.bound[lv] + (1ll << a.log2B) - 1) >> a.log2B) + L;
+      int g = persistent_grid(kfn, 256, 0);
+      g = std::min<int64_t>(g, (items + 255) / 256);
+      if (g < 1) g = 1;
+      if (lv == 0) {
+        if (single)
+          hipLaunchKernelGGL((lr_walk<true, false>), dim3(g), dim3(256), 0, stream, a);
+        else
+          hipLaunchKernelGGL((lr_walk<true, true>), dim3(g), dim3(256), 0, stream, a);
+      } else {
+        hipLaunchKernelGGL((lr_walk<false, false>), dim3(g), dim3(256), 0, stream, a);
+      }
+      PJ_HIP(hipGetLastError());
+      tm.mark(lv == 0 ? "walk0" : "walk_up");
+    }
+    // base ranking of the top level
+    const int top = p.levels;
+    const int cap_prev = p.cap[top - 1];
+    if (p.base_kind == 1) {
+      hipLaunchKernelGGL(lr_base_lds, dim3(1), dim3(kBaseThreads), 0, stream, b.link[top],
+                         b.srank[top], b.ctl, top, Li, cap_prev);
+    } else {
+      const int g = grid_for(p.bound[top], 256, gcap);
+      hipLaunchKernelGGL(wide_clear, dim3(g), dim3(256), 0, stream, b.wide_lnk, b.ctl, top, Li,
+                         cap_prev);
+      hipLaunchKernelGGL(wide_pred, dim3(g), dim3(256), 0, stream, b.link[top], b.wide_lnk, b.ctl,
+                         top, Li, cap_prev);
+      hipLaunchKernelGGL(wide_init, dim3(g), dim3(256), 0, stream, b.link[top], b.wide_lnk,
+                         b.wide_pl, b.ctl, top, Li, cap_prev);
+      for (int it = 0; it < p.wide_rounds; ++it)
+        hipLaunchKernelGGL(wide_jump, dim3(g), dim3(256), 0, stream, b.wide_pl, b.ctl, top, Li,
+                           cap_prev);
+      hipLaunchKernelGGL(wide_final, dim3(g), dim3(256), 0, stream, b.wide_pl, b.srank[top],
+                         b.ctl, top, Li, cap_prev);
+    }
+    PJ_HIP(hipGetLastError());
+    tm.mark("base");
+    // expand back down
+    for (int lv = top - 1; lv >= 1; --lv) {
+      const int g = grid_for(p.bound[lv], 256, gcap);
+      hipLaunchKernelGGL(lr_expand, dim3(g), dim3(256), 0, stream, b.state[lv], b.srank[lv + 1],
+                         b.srank[lv], b.ctl, lv, Li, p.cap[lv - 1], p.cap[lv]);
+    }
+    tm.mark("expand_up");
+    const int g0 = grid_for(n, 256, gcap);
+    if (single) {
+      if (o.to_tail)
+        hipLaunchKernelGGL((lr_expand0<false, true>), dim3(g0), dim3(256), 0, stream, b.state[0],
+                           b.srank[1], rank, off, b.ctl, Li, p.cap[0]);
+      else
+        hipLaunchKernelGGL((lr_expand0<false, false>), dim3(g0), dim3(256), 0, stream,
+                           b.state[0], b.srank[1], rank, off, b.ctl, Li, p.cap[0]);
+    } else {
+      if (o.to_tail)
+        hipLaunchKernelGGL((lr_expand0<true, true>), dim3(g0), dim3(256), 0, stream, b.state[0],
+                           b.srank[1], rank, off, b.ctl, Li, p.cap[0]);
+      else
+        hipLaunchKernelGGL((lr_expand0<true, false>), dim3(g0), dim3(256), 0, stream, b.state[0],
+                           b.srank[1], rank, off, b.ctl, Li, p.cap[0]);
+    }
+    PJ_HIP(hipGetLastError());
+    tm.mark("expand0");
+  }
+
+  if (o.validate && n0 > 0) {
+    const int g = grid_for(n, 256, gcap);
+    hipLaunchKernelGGL(chk_clear, dim3(g), dim3(256), 0, stream, b.chk, n);
+    if (single) {
+      hipLaunchKernelGGL(chk_count<false>, dim3(g), dim3(256), 0, stream, succ, rank, off, Li, n,
+                         o.to_tail, b.chk, b.lerr);
+      hipLaunchKernelGGL(chk_perm<false>, dim3(g), dim3(256), 0, stream, b.chk, off, Li, n,
+                         b.lerr);
+    } else {
+      hipLaunchKernelGGL(chk_count<true>, dim3(g), dim3(256), 0, stream, succ, rank, off, Li, n,
+                         o.to_tail, b.chk, b.lerr);
+      hipLaunchKernelGGL(chk_perm<true>, dim3(g), dim3(256), 0, stream, b.chk, off, Li, n,
+                         b.lerr);
+    }
+    PJ_HIP(hipGetLastError());
+    tm.mark("validate");
+  }
+  if (status) {
+    hipLaunchKernelGGL(lr_status, dim3(grid_for(L, 256, 1024)), dim3(256), 0, stream,
+                       p.algo == PJ_ALGO_RULING_SET && !p.small ? b.ctl : nullptr, b.lerr,
+                       b.ltails, off, Li, n, check_total ? 1 : 0, check_tails ? 1 : 0, status);
+    PJ_HIP(hipGetLastError());
+  }
+
+  int result = PJ_OK;
+  if (want_status) {
+    std::vector<int32_t> hs((size_t)L);
+    PJ_HIP(hipMemcpyAsync(hs.data(), status, sizeof(int32_t) * L, hipMemcpyDeviceToHost, stream));
+    PJ_HIP(hipStreamSynchronize(stream));
+    for (int64_t l = 0; l < L; ++l)
+      if (hs[l] != PJ_OK) {
+        result = hs[l];
+        break;
+      }
+  }
+  if (st) {
+    PJ_TRY(tm.finish(st));
+    st->algo = p.algo;
+    st->levels = p.levels;
+    st->base_kind = p.small ? 0 : p.base_kind;
+    LrCtl hc{};
+    PJ_HIP(hipMemcpyAsync(&hc, b.ctl, sizeof hc, hipMemcpyDeviceToHost, stream));
+    PJ_HIP(hipStreamSynchronize(stream));
+    st->level_nodes[0] = n0;
+    for (int l = 1; l <= p.levels && l <= PJ_MAX_LEVELS; ++l)
+      st->level_nodes[l] = hc.lv[l - 1].r + L + std::min(hc.lv[l - 1].dyn, p.cap[l - 1]);
+    st->status = result;
+  }
+  PJ_TRY(workspace_release(ws));
+  return result;
+}
+
+}  // namespace
+
+size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single) {
+  pj_opts o = resolved_opts(user);
+  Plan p = make_plan(n0, L, n0, o);
+  Buffers b;
+  return carve(p, L, single, o.validate != 0, o.validate && !o.d_status, nullptr, &b);
+}
+
+}  // namespace pj
+
+extern "C" {
+
+int pj_list_rank_ex(const int32_t* succ, int64_t n, int32_t* rank, const pj_opts* opts,
+                    pj_stream_t stream) {
+  if (n < 0) return PJ_EINVAL;
+  return pj::list_rank_impl(succ, nullptr, 1, nullptr, n, rank, opts, (hipStream_t)stream);
+}
+
+int pj_list_rank(const int32_t* succ, int64_t n, int32_t* rank, pj_stream_t stream) {
+  return pj_list_rank_ex(succ, n, rank, nullptr, stream);
+}
+
+int pj_list_rank_batched_ex(const int32_t* succ, const int64_t* offsets, int64_t L,
+                            int32_t* rank, const pj_opts* opts, pj_stream_t stream) {
+  if (!offsets || L < 0) return PJ_EINVAL;
+  return pj::list_rank_impl(succ, offsets, L, opts ? opts->h_offsets : nullptr, 0, rank, opts,
+                            (hipStream_t)stream);
+}
+
+int pj_list_rank_batched(const int32_t* succ, const int64_t* offsets, int64_t L, int32_t* rank,
+                         pj_stream_t stream) {
+  return pj_list_rank_batched_ex(succ, offsets, L, rank, nullptr, stream);
+}
+
+size_t pj_list_rank_workspace_bytes(int64_t total_nodes, int64_t L, const pj_opts* opts) {
+  if (total_nodes < 0 || L < 1) return 0;
+  return pj::list_rank_workspace(total_nodes, L, opts, L == 1);
+}
+
+}  // extern "C"

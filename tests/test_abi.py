@@ -1,0 +1,91 @@
+"""The C ABI: the built library loads without a GPU and exports every entry
+point include/ptrjump.h declares; the Python binding knows them all; the
+header's struct layouts match the binding's ctypes mirrors."""
+
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+from conftest import ROOT
+
+HEADER = os.path.join(ROOT, "include", "ptrjump.h")
+LIB = os.path.join(ROOT, "paper_1002_4482_amd", "libptrjump.so")
+
+
+def declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pj_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libptrjump.so not built (run __graft_entry__.build())")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for must in ("pj_list_rank", "pj_connected_components", "pj_list_rank_batched",
+                 "pj_connected_components_batched", "pj_strerror"):
+        assert must in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    missing = [n for n in declared_functions() if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_header():
+    from paper_1002_4482_amd import _lib
+    assert set(_lib.exported_names()) == set(declared_functions())
+
+
+def test_exports_are_c_symbols():
+    out = subprocess.run(["nm", "-D", "--defined-only", LIB], capture_output=True, text=True,
+                         check=True).stdout
+    syms = {line.split()[-1] for line in out.splitlines() if line.strip()}
+    for n in declared_functions():
+        assert n in syms, f"{n} is not an unmangled export"
+
+
+def test_host_only_calls(lib):
+    from paper_1002_4482_amd import _lib
+    L = _lib.load()
+    assert L.pj_strerror(0) == b"ok"
+    assert L.pj_strerror(-4).startswith(b"input is not")
+    assert L.pj_version() >= 10000
+    o = _lib.PjOpts()
+    L.pj_opts_init(ctypes.byref(o))
+    assert o.algo == 0 and o.seed != 0
+    # workspace sizing is host arithmetic
+    assert L.pj_list_rank_workspace_bytes(1 << 20, 1, None) > 8 * (1 << 20)
+    assert L.pj_cc_workspace_bytes(1 << 20, 1 << 22, 1, None) >= 8 * (1 << 20)
+
+
+def _c_sizeof(struct, field=None):
+    src = ("#include <stddef.h>\n#include <stdio.h>\n#include \"ptrjump.h\"\n"
+           f"int main(void){{printf(\"%zu\", {'offsetof(' + struct + ',' + field + ')' if field else 'sizeof(' + struct + ')'});return 0;}}\n")
+    return src
+
+
+def test_struct_layout_matches_ctypes(tmp_path):
+    from paper_1002_4482_amd import _lib
+    checks = [("pj_opts", None, ctypes.sizeof(_lib.PjOpts)),
+              ("pj_stats", None, ctypes.sizeof(_lib.PjStats))]
+    for f, _ in _lib.PjOpts._fields_:
+        checks.append(("pj_opts", f, getattr(_lib.PjOpts, f).offset))
+    for f, _ in _lib.PjStats._fields_:
+        checks.append(("pj_stats", f, getattr(_lib.PjStats, f).offset))
+    for i, (s, f, want) in enumerate(checks):
+        c = tmp_path / f"t{i}.c"
+        c.write_text(_c_sizeof(s, f))
+        exe = tmp_path / f"t{i}"
+        subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(c), "-o", str(exe)],
+                       check=True)
+        got = int(subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout)
+        assert got == want, (s, f, got, want)

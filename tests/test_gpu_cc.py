@@ -1,0 +1,132 @@
+"""GPU parity for connected components: the HIP Shiloach-Vishkin path through
+the C ABI against the union-find oracle, bit-exact on min-id labels."""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1002_4482_amd as pj
+    pj.load()
+    return pj
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run(pj, src, dst, n, **kw):
+    out = pj.connected_components(dev(src), dev(dst), n, **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,m", [(1, 0), (1, 3), (2, 1), (10, 0), (100, 50), (1000, 1000),
+                                 (5000, 40000), (100_003, 70_001), (300_000, 1_000_003),
+                                 (1 << 20, 1 << 22)])
+def test_random_graph_matches_oracle(pj, n, m):
+    src, dst = W.random_graph(n, m, n + m)
+    assert np.array_equal(run(pj, src, dst, n), oracle.connected_components(src, dst, n))
+
+
+@pytest.mark.parametrize("n,m,groups", [(4096, 8192, 64), (200_000, 600_000, 1024),
+                                        (1 << 20, 1 << 22, 1024)])
+def test_planted_matches_oracle(pj, n, m, groups):
+    src, dst, _ = W.planted_graph(n, m, groups, 3)
+    got = run(pj, src, dst, n)
+    assert np.array_equal(got, oracle.connected_components(src, dst, n))
+    assert len(np.unique(got)) == groups
+
+
+@pytest.mark.parametrize("family", ["lists", "trees2", "trees7", "path_up", "path_down", "star",
+                                    "self_loops"])
+def test_graph_families(pj, family):
+    n = 100_000
+    if family == "lists":
+        src, dst = W.list_graph(n, 37, 1)
+    elif family == "trees2":
+        src, dst = W.random_tree_graph(n, 2, 11, 2)
+    elif family == "trees7":
+        src, dst = W.random_tree_graph(n, 7, 5, 3)
+    elif family == "path_up":
+        src = np.arange(n - 1, dtype=np.int32)
+        dst = src + 1
+    elif family == "path_down":
+        dst = np.arange(n - 1, dtype=np.int32)
+        src = dst + 1
+        src, dst = src[::-1].copy(), dst[::-1].copy()
+    elif family == "star":
+        src = np.full(n - 1, n // 2, dtype=np.int32)
+        dst = np.delete(np.arange(n, dtype=np.int32), n // 2)
+    else:
+        src = np.arange(n, dtype=np.int32)
+        dst = src.copy()
+    want = oracle.connected_components(src, dst, n)
+    got, st = pj.connected_components(dev(src), dev(dst), n, return_stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    # Shiloach-Vishkin round bound floor(log_{3/2} n) + 2
+    assert st["rounds"] <= int(np.floor(np.log(n) / np.log(1.5))) + 2 + 1
+
+
+def test_unaligned_and_status(pj):
+    n, m = 50_000, 120_001
+    src, dst = W.random_graph(n, m, 8)
+    # views starting one element in: not 16-byte aligned
+    d_src = dev(np.concatenate([[0], src]).astype(np.int32))[1:]
+    d_dst = dev(np.concatenate([[0], dst]).astype(np.int32))[1:]
+    st = torch.full((1,), 5, dtype=torch.int32, device="cuda")
+    got = pj.connected_components(d_src, d_dst, n, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == 0
+    assert np.array_equal(got.cpu().numpy(), oracle.connected_components(src, dst, n))
+    bad = dst.copy()
+    bad[17] = n + 3
+    pj.connected_components(dev(src), dev(bad), n, status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == oracle.EINVAL
+
+
+def test_full_size_uniform_and_planted(pj):
+    n, m = 1 << 22, 1 << 25
+    for kind in ("uniform", "planted"):
+        if kind == "uniform":
+            src, dst = W.random_graph(n, m, W.SEED_BASE + 3)
+        else:
+            src, dst, _ = W.planted_graph(n, m, 1024, W.SEED_BASE + 3)
+        got = run(pj, src, dst, n)
+        assert np.array_equal(got, oracle.connected_components(src, dst, n)), kind
+
+
+def test_batched_matches_oracle(pj):
+    rng = np.random.default_rng(4)
+    graphs = []
+    for g in range(300):
+        n = int(np.floor(2 ** rng.uniform(0, 14)))
+        m = int(n * rng.uniform(0, 8))
+        s, d = W.random_graph(n, m, 1000 + g)
+        graphs.append((n, s, d))
+    graphs.insert(3, (0, np.empty(0, np.int32), np.empty(0, np.int32)))
+    voff = np.zeros(len(graphs) + 1, np.int64)
+    eoff = np.zeros(len(graphs) + 1, np.int64)
+    voff[1:] = np.cumsum([g[0] for g in graphs])
+    eoff[1:] = np.cumsum([len(g[1]) for g in graphs])
+    src = np.concatenate([g[1] for g in graphs]).astype(np.int32)
+    dst = np.concatenate([g[2] for g in graphs]).astype(np.int32)
+    want = oracle.connected_components_batched(src, dst, voff, eoff)
+    got = pj.connected_components_batched(dev(src), dev(dst), dev(voff), dev(eoff),
+                                          h_vtx_off=voff, h_edge_off=eoff)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    got2 = pj.connected_components_batched(dev(src), dev(dst), dev(voff), dev(eoff))
+    torch.cuda.synchronize()
+    assert np.array_equal(got2.cpu().numpy(), want)

@@ -1,0 +1,233 @@
+"""GPU parity for list ranking: the HIP path through the C ABI against the CPU
+oracle, element by element, bit-exact (integer work).
+
+Sizes span the one-workgroup path, several walk levels, ragged tails and the
+full 2^26-node benchmark list (checked there by the closed form
+rank[order[k]] = k, which holds at any size, plus oracle-computed samples).
+"""
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pj():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1002_4482_amd as pj
+    pj.load()
+    return pj
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def run(pj, succ, **kw):
+    out = pj.list_rank(dev(succ), **kw)
+    torch.cuda.synchronize()
+    return out.cpu().numpy()
+
+
+SIZES = [1, 2, 3, 64, 1000, 8192, 8193, 65537, 300_007, (1 << 20) + 13]
+
+
+@pytest.mark.parametrize("algo", ["ruling_set", "wyllie"])
+@pytest.mark.parametrize("n", SIZES)
+def test_random_list_matches_oracle(pj, algo, n):
+    succ = W.random_list(n, W.SEED_BASE + n)
+    got = run(pj, succ, algo=algo)
+    assert np.array_equal(got, oracle.list_rank(succ))
+
+
+@pytest.mark.parametrize("layout", ["sequential", "blocked", "reversed"])
+@pytest.mark.parametrize("n", [5000, 123_457, 1 << 20])
+def test_layouts_match_oracle(pj, layout, n):
+    if layout == "sequential":
+        succ = W.sequential_list(n)
+    elif layout == "blocked":
+        succ = W.blocked_list(n, 4096, 11)
+    else:  # list runs from the highest id down to 0
+        succ = np.arange(-1, n - 1, dtype=np.int32)
+    want = oracle.list_rank(succ)
+    for algo in ("ruling_set", "wyllie"):
+        assert np.array_equal(run(pj, succ, algo=algo), want), algo
+
+
+def test_paper_tail_convention_and_to_tail(pj):
+    n = 200_003
+    succ = W.random_list(n, 5)
+    want = oracle.list_rank(succ)
+    selfl = W.to_self_loop_tails(succ)
+    for algo in ("ruling_set", "wyllie"):
+        assert np.array_equal(run(pj, selfl, algo=algo), want)
+        assert np.array_equal(run(pj, succ, algo=algo, to_tail=True), n - 1 - want)
+
+
+@pytest.mark.parametrize("params", [
+    dict(spacing=2), dict(spacing=4, spacing_up=2), dict(spacing=64, spacing_up=32),
+    dict(spacing=1024), dict(max_walk=16), dict(cutoff=64), dict(seed=12345),
+    dict(block=64), dict(spacing=8, cutoff=256, max_walk=20, seed=7),
+])
+def test_parameters_do_not_change_ranks(pj, params):
+    n = 400_009
+    succ = W.random_list(n, 99)
+    assert np.array_equal(run(pj, succ, **params), oracle.list_rank(succ))
+
+
+def test_adversarial_long_sublists(pj):
+    # every splitter block's nodes visited consecutively after all others:
+    # sequential order with a large spacing forces cut points
+    n = 1 << 18
+    succ = W.sequential_list(n)
+    assert np.array_equal(run(pj, succ, spacing=65536, max_walk=16), np.arange(n))
+
+
+@pytest.mark.parametrize("bad,why", [
+    ("two_tails", "two lists"), ("cycle", "no tail"), ("detached_cycle", "list + cycle"),
+    ("out_of_range", "bad id"), ("branch", "two heads"),
+])
+@pytest.mark.parametrize("algo", ["ruling_set", "wyllie"])
+@pytest.mark.parametrize("n", [3000, 100_000])
+def test_malformed_lists_are_reported(pj, bad, why, algo, n):
+    succ = W.random_list(n, 3).copy()
+    order = np.argsort(oracle.list_rank(succ))
+    if bad == "two_tails":
+        succ[order[n // 2]] = -1
+    elif bad == "cycle":
+        succ[order[-1]] = order[0]
+    elif bad == "detached_cycle":
+        succ[order[n // 2 - 1]] = -1
+        succ[order[-1]] = order[n // 2]
+    elif bad == "out_of_range":
+        succ[order[7]] = n + 5
+    elif bad == "branch":
+        succ[order[10]] = order[20]
+    assert oracle.list_rank_status(succ)[0] == oracle.EBADLIST
+    status = torch.zeros(1, dtype=torch.int32, device="cuda")
+    pj.list_rank(dev(succ), algo=algo, validate=True, status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == oracle.EBADLIST, why
+
+
+def test_validate_accepts_good_lists(pj):
+    for n in (1, 7, 9000, 300_000):
+        succ = W.random_list(n, n)
+        for algo in ("ruling_set", "wyllie"):
+            status = torch.full((1,), 77, dtype=torch.int32, device="cuda")
+            got = pj.list_rank(dev(succ), algo=algo, validate=True, status=status)
+            torch.cuda.synchronize()
+            assert int(status.item()) == 0
+            assert np.array_equal(got.cpu().numpy(), oracle.list_rank(succ))
+
+
+def test_empty_list_is_noop(pj):
+    out = pj.list_rank(torch.empty(0, dtype=torch.int32, device="cuda"))
+    torch.cuda.synchronize()
+    assert out.numel() == 0
+
+
+def test_repeatable(pj):
+    succ = dev(W.random_list(1 << 20, 1))
+    a = pj.list_rank(succ)
+    b = pj.list_rank(succ, seed=2, spacing=32)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+def test_full_size_uniform_closed_form_and_samples(pj):
+    """The 2^26-node uniform list at the benchmark's launch configuration."""
+    n = 1 << 26
+    succ, order = W.random_list_with_order(n, W.SEED_BASE + 2)
+    d_succ = dev(succ)
+    got = pj.list_rank(d_succ)
+    torch.cuda.synchronize()
+    d_order = dev(order).long()
+    want = torch.arange(n, dtype=torch.int32, device="cuda")
+    assert torch.equal(got[d_order], want)
+    # sampled nodes against the oracle's ranks
+    ref = oracle.list_rank(succ)
+    idx = np.random.default_rng(0).integers(0, n, 100_000)
+    assert np.array_equal(got.cpu().numpy()[idx], ref[idx])
+    del d_succ, got, d_order, want
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("layout", ["sequential", "blocked"])
+def test_full_size_other_layouts(pj, layout):
+    n = 1 << 26
+    if layout == "sequential":
+        succ = W.sequential_list(n)
+        order = None
+    else:
+        succ, order = W.blocked_list_with_order(n, 4096, W.SEED_BASE + 2)
+    for algo in ("ruling_set", "wyllie"):
+        got = pj.list_rank(dev(succ), algo=algo)
+        torch.cuda.synchronize()
+        if order is None:
+            assert torch.equal(got, torch.arange(n, dtype=torch.int32, device="cuda")), algo
+        else:
+            assert torch.equal(got[dev(order).long()],
+                               torch.arange(n, dtype=torch.int32, device="cuda")), algo
+        del got
+    torch.cuda.empty_cache()
+
+
+# ------------------------------------------------------------------ batched
+def batched_case(L, lo, hi, seed):
+    succ, off = W.batched_lists(L, lo, hi, seed)
+    return succ, off
+
+
+@pytest.mark.parametrize("L,lo,hi", [(1, 3, 4), (5, 0, 3), (100, 0, 10), (700, 6, 14),
+                                     (64, 12, 17), (3000, 0, 6)])
+@pytest.mark.parametrize("algo", ["ruling_set", "wyllie"])
+def test_batched_matches_oracle(pj, L, lo, hi, algo):
+    succ, off = batched_case(L, lo, hi, L * 31 + lo)
+    status, want = oracle.list_rank_batched(succ, off)
+    assert (status == 0).all()
+    got = pj.list_rank_batched(dev(succ), dev(off), h_offsets=off, algo=algo)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    # without the host copy of the offsets
+    got2 = pj.list_rank_batched(dev(succ), dev(off), algo=algo)
+    torch.cuda.synchronize()
+    assert np.array_equal(got2.cpu().numpy(), want)
+
+
+def test_batched_with_empty_lists_and_statuses(pj):
+    lists = [W.random_list(s, s) for s in (0, 5, 0, 0, 1, 20000, 3, 0)]
+    succ, off = W.concat_lists(lists)
+    bad = succ.copy()
+    # list 5 (20000 nodes) gets a second tail
+    a = off[5]
+    seg = bad[a:off[6]]
+    seg[np.nonzero(seg != -1)[0][0]] = -1
+    for algo in ("ruling_set", "wyllie"):
+        st = torch.full((8,), 9, dtype=torch.int32, device="cuda")
+        got = pj.list_rank_batched(dev(succ), dev(off), h_offsets=off, algo=algo, status=st,
+                                   validate=True)
+        torch.cuda.synchronize()
+        assert st.cpu().numpy().tolist() == [0] * 8
+        assert np.array_equal(got.cpu().numpy(), oracle.list_rank_batched(succ, off)[1])
+        st.fill_(9)
+        pj.list_rank_batched(dev(bad), dev(off), h_offsets=off, algo=algo, status=st,
+                             validate=True)
+        torch.cuda.synchronize()
+        assert st.cpu().numpy()[5] == oracle.EBADLIST
+
+
+def test_batched_equals_per_list(pj):
+    succ, off = batched_case(50, 4, 15, 77)
+    d_succ = dev(succ)
+    got = pj.list_rank_batched(d_succ, dev(off), h_offsets=off)
+    for i in range(50):
+        one = pj.list_rank(d_succ[off[i]:off[i + 1]].clone())
+        torch.cuda.synchronize()
+        assert torch.equal(one, got[off[i]:off[i + 1]])
