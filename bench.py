@@ -1,0 +1,328 @@
+#!/usr/bin/env python3
+"""Benchmark: list ranking and connected components on one MI355X.
+
+One step = one full solve through the C ABI.  The headline workload is the
+uniform random list of n = 2^26 nodes ranked by the random-splitter (ruling
+set) path, inputs resident in HBM.  Extra workloads (Wyllie, other layouts,
+the 2^20 list, components on 2^22 vertices / 2^25 pairs, the batched 4096-list
+set against per-list launches) are reported under "extras".
+
+Prints progress on stderr and ONE JSON line on stdout.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import workloads as W  # noqa: E402
+
+METRIC = "list-rank nodes/s & CC edges/s at 1 GPU; batched vs plain speedup; p99 lat"
+HBM_PEAK_GBS = 8000.0
+LR_BYTES_PER_NODE = 8   # algorithmic: succ read once + rank written once
+CC_BYTES_PER_PAIR = 8   # algorithmic: both ends read once
+CC_BYTES_PER_VERTEX = 4  # algorithmic: label written once
+PROFILE_DIR = os.path.join(ROOT, "profiles")
+
+
+def log(*a):
+    print("[bench]", *a, file=sys.stderr, flush=True)
+
+
+def source_hash(*names):
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_1002_4482_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(name, src_files):
+    """HBM bytes per launch from a committed counter summary, if the kernel
+    source it was taken from is unchanged; else None."""
+    path = os.path.join(PROFILE_DIR, name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("source_hash") != source_hash(*src_files):
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def timed(torch, fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    t0.record()
+    for _ in range(steps):
+        fn()
+    t1.record()
+    torch.cuda.synchronize()
+    return t0.elapsed_time(t1) / steps
+
+
+def phase_means(stats_list):
+    acc = {}
+    for st in stats_list:
+        for name, ms in st["phase_list"]:
+            acc.setdefault(name, []).append(ms)
+    return {k: float(np.mean(v)) for k, v in acc.items()}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--no-extras", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--log2n", type=int, default=26)
+    ap.add_argument("--workload", default="c2u",
+                    choices=["c2u", "c2s", "c2b", "c2u_wyllie", "c1", "c3u", "c3p", "c4"],
+                    help="c2u (default) is the headline; the others time one workload "
+                         "alone (for profiling) and print its own JSON line")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+                          "n_gpus": args.gpus}), flush=True)
+        sys.exit(2)
+
+    import torch
+    import paper_1002_4482_amd as pj
+
+    pj.load()
+    dev = torch.device("cuda:0")
+    n = 1 << args.log2n
+    if args.workload != "c2u":
+        print(json.dumps(single_workload(torch, pj, dev, args)), flush=True)
+        return
+
+    log(f"generating uniform random list n=2^{args.log2n}")
+    succ, order = W.random_list_with_order(n, W.SEED_BASE + 2)
+    d_succ = torch.from_numpy(succ).to(dev)
+    d_rank = torch.empty_like(d_succ)
+
+    def step():
+        pj.list_rank(d_succ, d_rank, algo="ruling_set")
+
+    log(f"timing ruling set: warmup {args.warmup}, steps {args.steps}")
+    ms = timed(torch, step, args.steps, args.warmup)
+    # correctness of what was timed: closed form rank[order[k]] = k
+    ok = bool(torch.equal(d_rank[torch.from_numpy(order).to(dev).long()],
+                          torch.arange(n, dtype=torch.int32, device=dev)))
+    log(f"ruling set {ms:.3f} ms/step, correct={ok}")
+    if not ok:
+        raise SystemExit("ranking mismatch on the timed workload")
+
+    # per-phase device times (HIP events recorded by the library on its stream)
+    stats = []
+    for _ in range(max(3, min(args.steps, 10))):
+        _, st = pj.list_rank(d_succ, d_rank, algo="ruling_set", return_stats=True)
+        stats.append(st)
+    phases = phase_means(stats)
+    walk_ms = phases.get("walk0", float("nan"))
+    achieved = LR_BYTES_PER_NODE * n / (walk_ms * 1e-3) / 1e9
+    traffic = traffic_from_profile("walk0_u26_traffic.json", ["list_rank.hip"])
+    roofline = {
+        "bound": "hbm",
+        "achieved": round(achieved, 1),
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4),
+        "traffic": traffic,
+        "kernel": "lr_walk level 0 (sublist walks)",
+        "kernel_ms": round(walk_ms, 4),
+        "bytes_per_node": LR_BYTES_PER_NODE,
+    }
+    path_gbs = LR_BYTES_PER_NODE * n / (ms * 1e-3) / 1e9
+    log(f"phases {phases}")
+
+    extras = {
+        "phases_ms": {k: round(v, 4) for k, v in phases.items()},
+        "levels": stats[-1]["levels"],
+        "level_nodes": stats[-1]["level_nodes"],
+        "path_frac_of_hbm": round(path_gbs / HBM_PEAK_GBS, 4),
+    }
+    if not args.no_extras:
+        extras.update(run_extras(torch, pj, dev, d_succ, d_rank, n, args))
+    del d_succ, d_rank
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu:
+        import oracle
+        log("timing the CPU oracle on the same list (one run, 1 thread)")
+        t = time.perf_counter()
+        ref = oracle.list_rank(succ)
+        dt = time.perf_counter() - t
+        assert np.array_equal(ref[order], np.arange(n, dtype=np.int32))
+        cpu = {"value": round(n / dt, 1), "unit": "nodes/s", "cores": 1, "kind": "oracle",
+               "sample": f"one sequential walk over the whole 2^{args.log2n}-node uniform list "
+                         f"with validation ({dt:.2f} s)"}
+
+    out = {
+        "metric": METRIC,
+        "value": round(n / (ms * 1e-3), 1),
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int32",
+        "data": "synthetic",
+        "config": {
+            "workload": f"list ranking, one uniform random list, n=2^{args.log2n} int32 "
+                        "successors, ruling set (random splitters, recursive)",
+            "n": n,
+            "layout": "uniform random permutation",
+            "algo": "ruling_set",
+            "seed": W.SEED_BASE + 2,
+        },
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extras": extras,
+    }
+    print(json.dumps(out), flush=True)
+
+
+def single_workload(torch, pj, dev, args):
+    """Time one workload alone; returns its JSON record (phases included)."""
+    wl = args.workload
+    rec = {"workload": wl, "steps": args.steps, "warmup": args.warmup}
+    if wl in ("c2s", "c2b", "c2u_wyllie", "c1"):
+        n = 1 << (20 if wl == "c1" else args.log2n)
+        if wl == "c2s":
+            s = W.sequential_list(n)
+        elif wl == "c2b":
+            s = W.blocked_list(n, 4096, W.SEED_BASE + 2)
+        else:
+            s = W.random_list(n, W.SEED_BASE + (1 if wl == "c1" else 2))
+        algo = "wyllie" if wl == "c2u_wyllie" else "ruling_set"
+        ds = torch.from_numpy(s).to(dev)
+        dr = torch.empty_like(ds)
+        ms = timed(torch, lambda: pj.list_rank(ds, dr, algo=algo), args.steps, args.warmup)
+        _, st = pj.list_rank(ds, dr, algo=algo, return_stats=True)
+        rec.update(n=n, algo=algo, ms=round(ms, 4), nodes_per_s=round(n / (ms * 1e-3), 1),
+                   phases=st["phases"], levels=st["levels"], level_nodes=st["level_nodes"])
+    elif wl in ("c3u", "c3p"):
+        nv, m = 1 << 22, 1 << 25
+        if wl == "c3u":
+            src, dst = W.random_graph(nv, m, W.SEED_BASE + 3)
+        else:
+            src, dst, _ = W.planted_graph(nv, m, 1024, W.SEED_BASE + 3)
+        ds, dd = torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev)
+        lab = torch.empty(nv, dtype=torch.int32, device=dev)
+        ms = timed(torch, lambda: pj.connected_components(ds, dd, nv, lab), args.steps,
+                   args.warmup)
+        _, st = pj.connected_components(ds, dd, nv, lab, return_stats=True)
+        rec.update(n=nv, m=m, ms=round(ms, 4), edges_per_s=round(m / (ms * 1e-3), 1),
+                   rounds=st["rounds"], phases=st["phases"])
+    else:  # c4
+        bs, boff = W.batched_lists(4096, 6, 20, W.SEED_BASE + 4)
+        dbs, dboff = torch.from_numpy(bs).to(dev), torch.from_numpy(boff).to(dev)
+        dbr = torch.empty_like(dbs)
+        ms = timed(torch, lambda: pj.list_rank_batched(dbs, dboff, dbr, h_offsets=boff),
+                   args.steps, args.warmup)
+        _, st = pj.list_rank_batched(dbs, dboff, dbr, h_offsets=boff, return_stats=True)
+        rec.update(total_nodes=int(boff[-1]), ms=round(ms, 4),
+                   nodes_per_s=round(int(boff[-1]) / (ms * 1e-3), 1), phases=st["phases"],
+                   levels=st["levels"], level_nodes=st["level_nodes"])
+    log(json.dumps(rec))
+    return rec
+
+
+def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
+    ex = {}
+    steps = max(3, min(args.steps, 10))
+
+    # Wyllie on the same list
+    ms = timed(torch, lambda: pj.list_rank(d_succ, d_rank, algo="wyllie"), steps, 1)
+    ex["c2_uniform_wyllie_nodes_per_s"] = round(n / (ms * 1e-3), 1)
+    ex["c2_uniform_wyllie_ms"] = round(ms, 3)
+    log(f"wyllie uniform {ms:.3f} ms")
+
+    # other layouts
+    for name, s in (("sequential", W.sequential_list(n)),
+                    ("blocked", W.blocked_list(n, 4096, W.SEED_BASE + 2))):
+        ds = torch.from_numpy(s).to(dev)
+        for algo in ("ruling_set", "wyllie"):
+            ms = timed(torch, lambda: pj.list_rank(ds, d_rank, algo=algo), steps, 1)
+            ex[f"c2_{name}_{algo}_nodes_per_s"] = round(n / (ms * 1e-3), 1)
+            log(f"{name} {algo} {ms:.3f} ms")
+        del ds
+
+    # 2^20 list
+    n1 = 1 << 20
+    s1 = torch.from_numpy(W.random_list(n1, W.SEED_BASE + 1)).to(dev)
+    r1 = torch.empty_like(s1)
+    for algo in ("ruling_set", "wyllie"):
+        ms = timed(torch, lambda: pj.list_rank(s1, r1, algo=algo), 20, 3)
+        ex[f"c1_{algo}_nodes_per_s"] = round(n1 / (ms * 1e-3), 1)
+        ex[f"c1_{algo}_ms"] = round(ms, 4)
+        log(f"c1 {algo} {ms:.4f} ms")
+
+    # components
+    nv, m = 1 << 22, 1 << 25
+    for kind in ("uniform", "planted"):
+        if kind == "uniform":
+            src, dst = W.random_graph(nv, m, W.SEED_BASE + 3)
+        else:
+            src, dst, _ = W.planted_graph(nv, m, 1024, W.SEED_BASE + 3)
+        ds, dd = torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev)
+        lab = torch.empty(nv, dtype=torch.int32, device=dev)
+        ms = timed(torch, lambda: pj.connected_components(ds, dd, nv, lab), steps, 1)
+        _, st = pj.connected_components(ds, dd, nv, lab, return_stats=True)
+        ex[f"c3_{kind}_cc_edges_per_s"] = round(m / (ms * 1e-3), 1)
+        ex[f"c3_{kind}_cc_ms"] = round(ms, 3)
+        ex[f"c3_{kind}_rounds"] = st["rounds"]
+        ex[f"c3_{kind}_frac_of_hbm"] = round(
+            (CC_BYTES_PER_PAIR * m + CC_BYTES_PER_VERTEX * nv) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+        ex[f"c3_{kind}_phases_ms"] = {k: round(v, 3) for k, v in st["phases"].items()}
+        log(f"cc {kind} {ms:.3f} ms rounds {st['rounds']}")
+        del ds, dd, lab
+
+    # batched lists vs per-list launches
+    log("generating 4096 lists, sizes log-uniform in [2^6, 2^20]")
+    bs, boff = W.batched_lists(4096, 6, 20, W.SEED_BASE + 4)
+    total = int(boff[-1])
+    dbs = torch.from_numpy(bs).to(dev)
+    dboff = torch.from_numpy(boff).to(dev)
+    dbr = torch.empty_like(dbs)
+    views = [(dbs[boff[i]:boff[i + 1]], dbr[boff[i]:boff[i + 1]]) for i in range(4096)]
+
+    def plain():
+        for s, r in views:
+            pj.list_rank(s, r)
+
+    def batched():
+        pj.list_rank_batched(dbs, dboff, dbr, h_offsets=boff)
+
+    ms_b = timed(torch, batched, steps, 1)
+    ms_p = timed(torch, plain, 2, 1)
+    ex["c4_total_nodes"] = total
+    ex["c4_batched_ms"] = round(ms_b, 3)
+    ex["c4_plain_ms"] = round(ms_p, 3)
+    ex["c4_batched_nodes_per_s"] = round(total / (ms_b * 1e-3), 1)
+    ex["c4_speedup_batched_vs_plain"] = round(ms_p / ms_b, 3)
+    log(f"batched {ms_b:.3f} ms plain {ms_p:.3f} ms")
+    return ex
+
+
+if __name__ == "__main__":
+    main()

@@ -20,6 +20,10 @@
 //                         concurrent writes); the solve ends after the first
 //                         round with w[s] == 0.
 // Each pair is processed in both orientations by the thread that reads it.
+// Step 2 also drops every pair whose two ends already have the same parent
+// (they lie in one tree, and trees only ever merge), compacting the survivors
+// into the list the next round reads, together with the (D[i], D[j]) values it
+// read, which step 3 of the same round uses instead of gathering them again.
 // Concurrent writes to one root land in arbitrary order; every outcome is
 // one the arbitrary-CRCW algorithm allows: step 2 only hooks star roots onto
 // strictly smaller ids, step 3 only hooks stars that no step-2 hook touched,
@@ -42,7 +46,7 @@ struct CcCtl {
 __device__ __forceinline__ bool converged(const int32_t* w, int s) { return s > 1 && w[s - 1] == 0; }
 
 __global__ void sv_init(int32_t* __restrict__ D, int32_t* __restrict__ NS, int32_t* __restrict__ Q,
-                        int n, int32_t* w, int wlen, CcCtl* ctl) {
+                        int n, int32_t* w, unsigned long long* mcount, int wlen, CcCtl* ctl) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   for (int v = tid; v < n; v += stride) {
@@ -50,7 +54,10 @@ __global__ void sv_init(int32_t* __restrict__ D, int32_t* __restrict__ NS, int32
     NS[v] = 0;
     Q[v] = 0;
   }
-  for (int i = tid; i < wlen; i += stride) w[i] = 0;
+  for (int i = tid; i < wlen; i += stride) {
+    w[i] = 0;
+    mcount[i] = 0ull;
+  }
   if (tid == 0) {
     ctl->err = 0;
     ctl->rounds = 0;
@@ -88,78 +95,120 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
   if (__ballot(changed) && lane_id() == 0) w[s] = 1;
 }
 
-// Loads of four pairs at a time when the arrays allow it.
-template <typename F>
-__device__ __forceinline__ void for_each_pair(const int32_t* __restrict__ src,
-                                              const int32_t* __restrict__ dst, int64_t m, F f) {
-  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  const bool aligned = ((reinterpret_cast<uintptr_t>(src) | reinterpret_cast<uintptr_t>(dst)) & 15) == 0;
-  const int64_t m4 = aligned ? (m >> 2) : 0;
-  const int4* s4 = reinterpret_cast<const int4*>(src);
-  const int4* d4 = reinterpret_cast<const int4*>(dst);
-  for (int64_t q = tid; q < m4; q += stride) {
-    const int4 a = s4[q];
-    const int4 b = d4[q];
-    f(a.x, b.x);
-    f(a.y, b.y);
-    f(a.z, b.z);
-    f(a.w, b.w);
-  }
-  for (int64_t e = (m4 << 2) + tid; e < m; e += stride) f(src[e], dst[e]);
-}
+// Step 2, with compaction of the pairs that can still matter.  A workgroup
+// handles chunks of kHookPer * 256 pairs and reserves room for its survivors
+// with one atomic per chunk.
+constexpr int kHookPer = 8;
+constexpr int kHookWaves = 256 / kWave;
 
-// Step 2.
 __global__ void __launch_bounds__(256) sv_hook(const int32_t* __restrict__ src,
-                                               const int32_t* __restrict__ dst, int64_t m,
+                                               const int32_t* __restrict__ dst, int64_t m_host,
+                                               const unsigned long long* m_dev,
                                                int32_t* __restrict__ D,
                                                const int32_t* __restrict__ NS,
-                                               int32_t* __restrict__ Q, int n, int32_t* w, int s,
+                                               int32_t* __restrict__ Q, int n,
+                                               int32_t* __restrict__ osrc,
+                                               int32_t* __restrict__ odst,
+                                               int2* __restrict__ ocache,
+                                               unsigned long long* m_out, int32_t* w, int s,
                                                CcCtl* ctl) {
   if (converged(w, s)) return;
+  const int64_t m = m_dev ? (int64_t)*m_dev : m_host;
+  __shared__ int cnt[kHookPer][kHookWaves];
+  __shared__ unsigned long long chunk_base;
+  const int wave = threadIdx.x / kWave;
+  const int64_t chunk = 256 * kHookPer;
   bool hooked = false, bad = false;
-  for_each_pair(src, dst, m, [&](int u, int v) {
-    if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) {
-      bad = true;
-      return;
+  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < m; c0 += (int64_t)gridDim.x * chunk) {
+    int uu[kHookPer], vv[kHookPer], du[kHookPer], dv[kHookPer];
+    bool keep[kHookPer];
+#pragma unroll
+    for (int t = 0; t < kHookPer; ++t) {
+      const int64_t e = c0 + t * 256 + threadIdx.x;
+      keep[t] = false;
+      uu[t] = vv[t] = du[t] = dv[t] = 0;
+      if (e < m) {
+        const int u = src[e], v = dst[e];
+        if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) {
+          bad = true;
+        } else {
+          uu[t] = u;
+          vv[t] = v;
+          du[t] = D[u];
+          dv[t] = D[v];
+          keep[t] = du[t] != dv[t];
+        }
+      }
     }
-    const int du = D[u];
-    const int dv = D[v];
-    int a, b;
-    if (dv < du) {
-      a = du;
-      b = dv;
-    } else if (du < dv) {
-      a = dv;
-      b = du;
-    } else {
-      return;
+#pragma unroll
+    for (int t = 0; t < kHookPer; ++t) {
+      if (!keep[t]) continue;
+      int a, b;
+      if (dv[t] < du[t]) {
+        a = du[t];
+        b = dv[t];
+      } else {
+        a = dv[t];
+        b = du[t];
+      }
+      if (D[a] == a && NS[a] != s) {
+        D[a] = b;
+        Q[a] = s;
+        Q[b] = s;
+        hooked = true;
+      }
     }
-    if (D[a] == a && NS[a] != s) {
-      D[a] = b;
-      Q[a] = s;
-      Q[b] = s;
-      hooked = true;
+    // reserve output room for this chunk's survivors
+#pragma unroll
+    for (int t = 0; t < kHookPer; ++t) {
+      const uint64_t bm = __ballot(keep[t]);
+      if (lane_id() == 0) cnt[t][wave] = __popcll(bm);
     }
-  });
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      int total = 0;
+      for (int t = 0; t < kHookPer; ++t)
+        for (int q = 0; q < kHookWaves; ++q) {
+          const int c = cnt[t][q];
+          cnt[t][q] = total;
+          total += c;
+        }
+      chunk_base = total ? atomicAdd(m_out, (unsigned long long)total) : 0ull;
+    }
+    __syncthreads();
+    const unsigned long long cb = chunk_base;
+#pragma unroll
+    for (int t = 0; t < kHookPer; ++t) {
+      const uint64_t bm = __ballot(keep[t]);
+      if (keep[t]) {
+        const unsigned long long pos = cb + cnt[t][wave] + lanes_below(bm);
+        osrc[pos] = uu[t];
+        odst[pos] = vv[t];
+        ocache[pos] = make_int2(du[t], dv[t]);
+      }
+    }
+    __syncthreads();
+  }
   if (__ballot(hooked) && lane_id() == 0) w[s] = 1;
   if (__ballot(bad) && lane_id() == 0) atomicOr(&ctl->err, kErrRange);
 }
 
-// Step 3.
-__global__ void __launch_bounds__(256) sv_stagnant(const int32_t* __restrict__ src,
-                                                   const int32_t* __restrict__ dst, int64_t m,
+// Step 3 over the survivors of step 2, reading the parents step 2 saw.  A
+// cached value is stale only for a root that step 2 hooked; such a tree is
+// not stagnant, and hooking onto a node of it still joins the right trees.
+__global__ void __launch_bounds__(256) sv_stagnant(const int2* __restrict__ cache,
+                                                   const unsigned long long* m_dev,
                                                    int32_t* __restrict__ D,
                                                    const int32_t* __restrict__ NS,
-                                                   const int32_t* __restrict__ Q, int n,
-                                                   int32_t* w, int s) {
+                                                   const int32_t* __restrict__ Q, int32_t* w,
+                                                   int s) {
   if (converged(w, s)) return;
+  const int64_t m = (int64_t)*m_dev;
   bool hooked = false;
-  for_each_pair(src, dst, m, [&](int u, int v) {
-    if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) return;
-    const int du = D[u];
-    const int dv = D[v];
-    if (du == dv) return;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int2 c = cache[e];
+    const int du = c.x, dv = c.y;
     if (D[du] == du && NS[du] != s && Q[du] != s) {
       D[du] = dv;
       hooked = true;
@@ -167,7 +216,7 @@ __global__ void __launch_bounds__(256) sv_stagnant(const int32_t* __restrict__ s
       D[dv] = du;
       hooked = true;
     }
-  });
+  }
   if (__ballot(hooked) && lane_id() == 0) w[s] = 1;
 }
 
@@ -198,6 +247,7 @@ __global__ void __launch_bounds__(256) canon_min(const int32_t* __restrict__ D,
       const int64_t v = c0 + t * 256 + threadIdx.x;
       if (v >= n) break;
       const int r = D[v];
+      if ((int)v >= r) continue;  // M[r] starts at r: only smaller members matter
       if (r == leader) mymin = min(mymin, (int)v);
       else atomicMin(&M[r], (int)v);
     }
@@ -274,8 +324,12 @@ struct CcBuffers {
   int32_t* NS = nullptr;
   int32_t* Q = nullptr;
   int32_t* w = nullptr;
+  unsigned long long* mcount = nullptr;  // surviving pairs after step 2 of each round
   int32_t* gsrc = nullptr;
   int32_t* gdst = nullptr;
+  int32_t* es[2] = {};                   // compacted pair lists (ping-pong)
+  int32_t* ed[2] = {};
+  int2* cache = nullptr;                 // (D[i], D[j]) seen by step 2
   int32_t* status_tmp = nullptr;
 };
 
@@ -291,6 +345,13 @@ size_t cc_carve(int64_t n, int64_t m, int64_t G, bool batched, bool want_status,
   take(b->NS, (size_t)std::max<int64_t>(n, 1));
   take(b->Q, (size_t)std::max<int64_t>(n, 1));
   take(b->w, (size_t)wlen);
+  take(b->mcount, (size_t)wlen);
+  const size_t mm = (size_t)std::max<int64_t>(m, 1);
+  take(b->es[0], mm);
+  take(b->ed[0], mm);
+  take(b->es[1], mm);
+  take(b->ed[1], mm);
+  take(b->cache, mm);
   if (batched) {
     take(b->gsrc, (size_t)std::max<int64_t>(m, 1));
     take(b->gdst, (size_t)std::max<int64_t>(m, 1));
@@ -332,7 +393,8 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
   const int cus = device_info().cus;
   const int gcap = cus * 16;
   const int gv = grid_for(n, 256, gcap);
-  const int ge = grid_for((m + 3) / 4, 256, gcap);
+  const int ge = grid_for(m, 256, gcap);
+  const int gh = grid_for((m + kHookPer - 1) / kHookPer, 256, gcap);
   int32_t* D = label;
 
   const int32_t* es = src;
@@ -343,7 +405,8 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
     es = b.gsrc;
     ed = b.gdst;
   }
-  hipLaunchKernelGGL(sv_init, dim3(gv), dim3(256), 0, stream, D, b.NS, b.Q, ni, b.w, wlen, b.ctl);
+  hipLaunchKernelGGL(sv_init, dim3(gv), dim3(256), 0, stream, D, b.NS, b.Q, ni, b.w, b.mcount,
+                     wlen, b.ctl);
   PJ_HIP(hipGetLastError());
   tm.mark("sv0_init");
 
@@ -360,10 +423,15 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
       hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
       hipLaunchKernelGGL(sv_mark, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, b.w, s, b.ctl);
       if (m > 0) {
-        hipLaunchKernelGGL(sv_hook, dim3(ge), dim3(256), 0, stream, es, ed, m, D, b.NS, b.Q, ni,
-                           b.w, s, b.ctl);
-        hipLaunchKernelGGL(sv_stagnant, dim3(ge), dim3(256), 0, stream, es, ed, m, D, b.NS, b.Q,
-                           ni, b.w, s);
+        // round 1 reads the input pairs, later rounds the survivors of the last one
+        const int32_t* isrc = s == 1 ? es : b.es[(s - 1) & 1];
+        const int32_t* idst = s == 1 ? ed : b.ed[(s - 1) & 1];
+        const unsigned long long* mdev = s == 1 ? nullptr : b.mcount + (s - 1);
+        hipLaunchKernelGGL(sv_hook, dim3(gh), dim3(256), 0, stream, isrc, idst, m, mdev, D, b.NS,
+                           b.Q, ni, b.es[s & 1], b.ed[s & 1], b.cache, b.mcount + s, b.w, s,
+                           b.ctl);
+        hipLaunchKernelGGL(sv_stagnant, dim3(ge), dim3(256), 0, stream, b.cache, b.mcount + s, D,
+                           b.NS, b.Q, b.w, s);
       }
       hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
     }

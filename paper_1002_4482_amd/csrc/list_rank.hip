@@ -100,17 +100,21 @@ __global__ void lr_init(LrCtl* ctl, int n0, unsigned long long* lsum, int32_t* l
 // are exactly the non-tail successors, so
 //   head = size(size-1)/2 - sum of non-tail successors.
 // The same coalesced pass counts tails and flags out-of-range successors.
+template <bool kCopy>
 __global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restrict__ succ, int n,
+                                                          int32_t* __restrict__ copy,
                                                           unsigned long long* lsum,
                                                           int32_t* ltails, int32_t* lerr) {
   unsigned long long acc = 0;
   int tails = 0, bad = 0;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
-  const int n4 = (reinterpret_cast<uintptr_t>(succ) & 15) == 0 ? (n >> 2) : 0;
+  const bool vec = ((reinterpret_cast<uintptr_t>(succ) | reinterpret_cast<uintptr_t>(copy)) & 15) == 0;
+  const int n4 = vec ? (n >> 2) : 0;
   const int4* s4 = reinterpret_cast<const int4*>(succ);
   for (int q = tid; q < n4; q += stride) {
     const int4 v = s4[q];
+    if (kCopy) reinterpret_cast<int4*>(copy)[q] = v;
     int i = q << 2;
     int vs[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
@@ -125,6 +129,7 @@ __global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restr
   }
   for (int i = (n4 << 2) + tid; i < n; i += stride) {
     int s = succ[i];
+    if (kCopy) copy[i] = s;
     bool tail = (s == -1) | (s == i);
     bool range = (unsigned)s < (unsigned)n;
     tails += tail;
@@ -134,7 +139,22 @@ __global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restr
   acc = wave_sum(acc);
   tails = wave_sum(tails);
   bad = wave_sum(bad);
+  // one atomic per workgroup: atomics on a single address serialise
+  __shared__ unsigned long long s_acc[256 / kWave];
+  __shared__ int s_tails[256 / kWave], s_bad[256 / kWave];
+  const int w = threadIdx.x / kWave;
   if (lane_id() == 0) {
+    s_acc[w] = acc;
+    s_tails[w] = tails;
+    s_bad[w] = bad;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int i = 1; i < (int)(blockDim.x / kWave); ++i) {
+      acc += s_acc[i];
+      tails += s_tails[i];
+      bad += s_bad[i];
+    }
     if (acc) atomicAdd(lsum, acc);
     if (tails) atomicAdd(ltails, tails);
     if (bad) atomicOr(lerr, kErrRange);
@@ -144,9 +164,11 @@ __global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restr
 // Batched form: each wave owns chunks of 64*kChunk consecutive positions and
 // tracks the owning list while it advances.
 constexpr int kHfChunk = 16;
+template <bool kCopy>
 __global__ void __launch_bounds__(256) lr_headfind_batched(const int32_t* __restrict__ succ,
                                                            const int64_t* __restrict__ off, int L,
-                                                           int n, unsigned long long* lsum,
+                                                           int n, int32_t* __restrict__ copy,
+                                                           unsigned long long* lsum,
                                                            int32_t* ltails, int32_t* lerr) {
   const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
   const int nwaves = (gridDim.x * blockDim.x) / kWave;
@@ -171,6 +193,7 @@ __global__ void __launch_bounds__(256) lr_headfind_batched(const int32_t* __rest
         lend = off[l + 1];
       }
       int s = succ[g];
+      if (kCopy) copy[g] = s;
       int x = (int)(g - lbase);
       int size = (int)(lend - lbase);
       bool tail = (s == -1) | (s == x);
@@ -204,6 +227,8 @@ struct WalkArgs {
   const int32_t* ltails;             // level 0: tail counts
   int32_t* lerr;                     // per-list error bits
   int2* state;                       // {sublist id, weight before node} per node
+  int32_t* work;                     // level 0 packed form: successor copy, overwritten
+                                     // in place by (sublist id << kbits | offset)
   int2* link_out;                    // {next splitter, sublist weight} per splitter
   LrCtl* ctl;
   int L;
@@ -212,10 +237,15 @@ struct WalkArgs {
   int max_walk;
   int cap;       // cut points this level may create
   int cap_prev;  // cut points the level below could create
+  int kbits;     // level 0 packed form: bits of the in-sublist offset
   uint32_t seed;
 };
 
-template <bool kLevel0, bool kBatched>
+// kPacked (level 0): the successors are read from a.work, a copy made by the
+// head-find pass, and each visited slot is overwritten with the node's packed
+// state.  The read and the write then touch the same cache line, which costs
+// far less than a write to a second random line.
+template <bool kLevel0, bool kBatched, bool kPacked>
 __global__ void __launch_bounds__(256) lr_walk(WalkArgs a) {
   LrCtl* ctl = a.ctl;
   const int N = level_nodes(ctl, a.level, a.L, a.cap_prev);
@@ -224,9 +254,18 @@ __global__ void __launch_bounds__(256) lr_walk(WalkArgs a) {
   const int head_base = kLevel0 ? 0 : ctl->lv[a.level - 1].r;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->lv[a.level].r = r;
   const int items = r + a.L;
-  int* work = &ctl->lv[a.level].work;
   int* dyn = &ctl->lv[a.level].dyn;
   const uint32_t seed = a.seed;
+  // Work distribution: each workgroup owns a contiguous range of splitter
+  // ids and hands them to its lanes through an LDS counter.  (One global
+  // counter hit by every wave serialises at the memory side.)
+  __shared__ int wg_next;
+  const int per = (int)(((int64_t)items + gridDim.x - 1) / gridDim.x);
+  const int wg_lo = min(items, (int)((int64_t)blockIdx.x * per));
+  const int wg_hi = min(items, wg_lo + per);
+  if (threadIdx.x == 0) wg_next = wg_lo;
+  __syncthreads();
+  int* work = &wg_next;
 
   int sid = -1;       // sublist being walked, -1 = idle
   int x = 0;          // current node
@@ -248,7 +287,7 @@ __global__ void __launch_bounds__(256) lr_walk(WalkArgs a) {
       first = __shfl(first, leader);
       if (need) {
         const int item = first + lanes_below(needm);
-        if (item >= items) {
+        if (item >= wg_hi) {
           retired = true;
         } else if (item < r) {  // static splitter
           const int start = item << log2B;
@@ -312,7 +351,7 @@ __global__ void __launch_bounds__(256) lr_walk(WalkArgs a) {
       int y, w;
       bool tail;
       if (kLevel0) {
-        const int s = a.succ0[x];
+        const int s = kPacked ? a.work[x] : a.succ0[x];
         const int xl = (int)(x - base);
         tail = (s == -1) | (s == xl);
         if (!tail && (unsigned)s >= (unsigned)size) {
@@ -331,7 +370,8 @@ __global__ void __launch_bounds__(256) lr_walk(WalkArgs a) {
         y = in.x;
         w = in.y;
       }
-      store_pair(&a.state[x], sid, k);
+      if (kLevel0 && kPacked) a.work[x] = (sid << a.kbits) | k;
+      else store_pair(&a.state[x], sid, k);
       k += w;
       if (tail) {
         store_pair(&a.link_out[sid], -1, k);
@@ -545,18 +585,24 @@ __global__ void __launch_bounds__(256) lr_expand(const int2* __restrict__ state,
 }
 
 // Level 0: write the output ranks (from the head, or to the tail).
-template <bool kBatched, bool kToTail>
+template <bool kBatched, bool kToTail, bool kPacked>
 __global__ void __launch_bounds__(256) lr_expand0(const int2* __restrict__ state,
                                                   const int32_t* __restrict__ srank_up,
-                                                  int32_t* __restrict__ rank,
+                                                  int32_t* rank,
                                                   const int64_t* __restrict__ off, LrCtl* ctl,
-                                                  int L, int cap_here) {
+                                                  int L, int cap_here, int kbits) {
   const int N = ctl->lv[0].n;
   const int Nup = level_nodes(ctl, 1, L, cap_here);
   int bad = 0;
   const int stride = gridDim.x * blockDim.x;
   for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += stride) {
-    const int2 s = state[j];
+    int2 s;
+    if (kPacked) {
+      const int w = rank[j];
+      s = make_int2((int)((unsigned)w >> kbits), w & ((1 << kbits) - 1));
+    } else {
+      s = state[j];
+    }
     int v = 0;
     if ((unsigned)s.x < (unsigned)Nup) v = srank_up[s.x] + s.y;
     else bad = 1;
@@ -793,7 +839,16 @@ struct Plan {
   int cap[PJ_MAX_LEVELS + 1] = {};
   int wide_rounds = 0;
   int wy_rounds = 0;
+  bool packed = false;     // level 0 state packed into the output buffer
+  int kbits = 0;           // offset bits of the packed state
+  int max_walk0 = 0;       // cut length at level 0
 };
+
+inline int bits_for(int64_t v) {  // bits to hold values 0..v-1
+  int b = 0;
+  while ((int64_t(1) << b) < v) ++b;
+  return b;
+}
 
 Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o) {
   Plan p;
@@ -824,7 +879,24 @@ Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o) {
     const int spacing = lv == 0 ? o.spacing : o.spacing_up;
     p.log2B[lv] = ilog2(std::max(2, spacing));
     const int64_t r = (b + (1ll << p.log2B[lv]) - 1) >> p.log2B[lv];
-    p.cap[lv] = (int)(b / o.max_walk + 64);
+    int mw = o.max_walk;
+    if (lv == 0) {
+      // Pack (sublist id, offset) into 31 bits when the id space allows an
+      // offset of at least 4 bits; the cut length then bounds the offset.
+      p.packed = false;
+      for (int kb = bits_for(mw); kb >= 4; --kb) {
+        const int mwk = std::min(mw, 1 << kb);
+        const int64_t ids = r + L + b / mwk + 64;
+        if (bits_for(ids) + kb <= 31) {
+          p.packed = true;
+          p.kbits = kb;
+          mw = mwk;
+          break;
+        }
+      }
+      p.max_walk0 = mw;
+    }
+    p.cap[lv] = (int)(b / mw + 64);
     p.bound[lv + 1] = r + L + p.cap[lv];
     ++lv;
   }
@@ -870,7 +942,7 @@ size_t carve(const Plan& p, int64_t L, bool single, bool validate, bool want_sta
   }
   if (p.small) return bytes;
   for (int l = 0; l < p.levels; ++l) {
-    take(b->state[l], (size_t)p.bound[l]);
+    if (!(l == 0 && p.packed)) take(b->state[l], (size_t)p.bound[l]);
     take(b->link[l + 1], (size_t)p.bound[l + 1]);
     take(b->srank[l + 1], (size_t)p.bound[l + 1]);
   }
@@ -952,12 +1024,12 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
   if (n0 > 0 && p.algo == PJ_ALGO_WYLLIE) {
     if (o.validate || o.d_status) {
       if (single)
-        hipLaunchKernelGGL(lr_headfind_single, dim3(grid_for(n / 4 + 1, 256, gcap)), dim3(256),
-                           0, stream, succ, n, b.lsum, b.ltails, b.lerr);
+        hipLaunchKernelGGL(lr_headfind_single<false>, dim3(grid_for(n / 4 + 1, 256, 1024)),
+                           dim3(256), 0, stream, succ, n, nullptr, b.lsum, b.ltails, b.lerr);
       else
-        hipLaunchKernelGGL(lr_headfind_batched,
+        hipLaunchKernelGGL(lr_headfind_batched<false>,
                            dim3(grid_for(n / (kHfChunk * 4) + 1, 256, gcap)), dim3(256), 0,
-                           stream, succ, off, Li, n, b.lsum, b.ltails, b.lerr);
+                           stream, succ, off, Li, n, nullptr, b.lsum, b.ltails, b.lerr);
       check_tails = true;
       tm.mark("headfind");
     }
@@ -994,13 +1066,17 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     check_tails = true;
     tm.mark("small");
   } else if (n0 > 0) {
-    // level 0 head find
-    if (single)
-      hipLaunchKernelGGL(lr_headfind_single, dim3(grid_for(n / 4 + 1, 256, gcap)), dim3(256), 0,
-                         stream, succ, n, b.lsum, b.ltails, b.lerr);
-    else
-      hipLaunchKernelGGL(lr_headfind_batched, dim3(grid_for(n / (kHfChunk * 4) + 1, 256, gcap)),
-                         dim3(256), 0, stream, succ, off, Li, n, b.lsum, b.ltails, b.lerr);
+    // level 0 head find (and, in the packed form, the successor copy)
+    int32_t* copy = p.packed ? rank : nullptr;
+    if (single) {
+      auto k = p.packed ? lr_headfind_single<true> : lr_headfind_single<false>;
+      hipLaunchKernelGGL(k, dim3(grid_for(n / 4 + 1, 256, 1024)), dim3(256), 0, stream, succ, n,
+                         copy, b.lsum, b.ltails, b.lerr);
+    } else {
+      auto k = p.packed ? lr_headfind_batched<true> : lr_headfind_batched<false>;
+      hipLaunchKernelGGL(k, dim3(grid_for(n / (kHfChunk * 4) + 1, 256, gcap)), dim3(256), 0,
+                         stream, succ, off, Li, n, copy, b.lsum, b.ltails, b.lerr);
+    }
     PJ_HIP(hipGetLastError());
     tm.mark("headfind");
     check_total = true;
@@ -1015,32 +1091,26 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
       a.ltails = b.ltails;
       a.lerr = b.lerr;
       a.state = b.state[lv];
+      a.work = copy;
       a.link_out = b.link[lv + 1];
       a.ctl = b.ctl;
       a.L = Li;
       a.level = lv;
       a.log2B = p.log2B[lv];
-      a.max_walk = o.max_walk;
+      a.max_walk = lv == 0 ? p.max_walk0 : o.max_walk;
       a.cap = p.cap[lv];
       a.cap_prev = lv > 0 ? p.cap[lv - 1] : 0;
+      a.kbits = p.kbits;
       a.seed = level_seed(o.seed, lv);
-      const void* kfn;
-      if (lv == 0)
-        kfn = single ? (const void*)lr_walk<true, false> : (const void*)lr_walk<true, true>;
-      else
-        kfn = (const void*)lr_walk<false, false>;
+      void (*kfn)(WalkArgs);
+      if (lv > 0) kfn = lr_walk<false, false, false>;
+      else if (single) kfn = p.packed ? lr_walk<true, false, true> : lr_walk<true, false, false>;
+      else kfn = p.packed ? lr_walk<true, true, true> : lr_walk<true, true, false>;
       const int64_t items = ((p.bound[lv] + (1ll << a.log2B) - 1) >> a.log2B) + L;
-      int g = persistent_grid(kfn, 256, 0);
-      g = std::min<int64_t>(g, (items + 255) / 256);
+      int g = persistent_grid((const void*)kfn, 256, 0);
+      g = (int)std::min<int64_t>(g, (items + 255) / 256);
       if (g < 1) g = 1;
-      if (lv == 0) {
-        if (single)
-          hipLaunchKernelGGL((lr_walk<true, false>), dim3(g), dim3(256), 0, stream, a);
-        else
-          hipLaunchKernelGGL((lr_walk<true, true>), dim3(g), dim3(256), 0, stream, a);
-      } else {
-        hipLaunchKernelGGL((lr_walk<false, false>), dim3(g), dim3(256), 0, stream, a);
-      }
+      hipLaunchKernelGGL(kfn, dim3(g), dim3(256), 0, stream, a);
       PJ_HIP(hipGetLastError());
       tm.mark(lv == 0 ? "walk0" : "walk_up");
     }
@@ -1074,21 +1144,16 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     }
     tm.mark("expand_up");
     const int g0 = grid_for(n, 256, gcap);
+    void (*ex0)(const int2*, const int32_t*, int32_t*, const int64_t*, LrCtl*, int, int, int);
     if (single) {
-      if (o.to_tail)
-        hipLaunchKernelGGL((lr_expand0<false, true>), dim3(g0), dim3(256), 0, stream, b.state[0],
-                           b.srank[1], rank, off, b.ctl, Li, p.cap[0]);
-      else
-        hipLaunchKernelGGL((lr_expand0<false, false>), dim3(g0), dim3(256), 0, stream,
-                           b.state[0], b.srank[1], rank, off, b.ctl, Li, p.cap[0]);
+      if (o.to_tail) ex0 = p.packed ? lr_expand0<false, true, true> : lr_expand0<false, true, false>;
+      else ex0 = p.packed ? lr_expand0<false, false, true> : lr_expand0<false, false, false>;
     } else {
-      if (o.to_tail)
-        hipLaunchKernelGGL((lr_expand0<true, true>), dim3(g0), dim3(256), 0, stream, b.state[0],
-                           b.srank[1], rank, off, b.ctl, Li, p.cap[0]);
-      else
-        hipLaunchKernelGGL((lr_expand0<true, false>), dim3(g0), dim3(256), 0, stream, b.state[0],
-                           b.srank[1], rank, off, b.ctl, Li, p.cap[0]);
+      if (o.to_tail) ex0 = p.packed ? lr_expand0<true, true, true> : lr_expand0<true, true, false>;
+      else ex0 = p.packed ? lr_expand0<true, false, true> : lr_expand0<true, false, false>;
     }
+    hipLaunchKernelGGL(ex0, dim3(g0), dim3(256), 0, stream, b.state[0], b.srank[1], rank, off,
+                       b.ctl, Li, p.cap[0], p.kbits);
     PJ_HIP(hipGetLastError());
     tm.mark("expand0");
   }
