@@ -93,6 +93,9 @@ def main():
                     choices=["c2u", "c2s", "c2b", "c2u_wyllie", "c1", "c3u", "c3p", "c4"],
                     help="c2u (default) is the headline; the others time one workload "
                          "alone (for profiling) and print its own JSON line")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first copy a 256 MiB int32 tensor three times (a kernel of known "
+                         "traffic, to scale HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -106,6 +109,15 @@ def main():
     pj.load()
     dev = torch.device("cuda:0")
     n = 1 << args.log2n
+    if args.calibrate_copy:
+        a = torch.arange(1 << 26, dtype=torch.int32, device=dev)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 256 MiB")
+        del a, b
     if args.workload != "c2u":
         print(json.dumps(single_workload(torch, pj, dev, args)), flush=True)
         return
