@@ -76,7 +76,7 @@ typedef struct pj_opts {
                                  consecutive node ids (power of two, 2..65536) */
     int32_t spacing_up;       /* ruling set, recursion levels: same meaning */
     int32_t cutoff;           /* ruling set: a level with at most this many nodes is ranked
-                                 by one workgroup in LDS (64..8192) */
+                                 by one workgroup in LDS (64..16384) */
     int32_t max_walk;         /* ruling set: a sublist walk is cut after this many nodes,
                                  the cut node becoming a new splitter (>= 16) */
     uint64_t seed;            /* splitter hash seed (results do not depend on it) */
@@ -138,8 +138,42 @@ int pj_list_rank_batched(const int32_t *succ, const int64_t *offsets, int64_t L,
 int pj_list_rank_batched_ex(const int32_t *succ, const int64_t *offsets, int64_t L,
                             int32_t *rank, const pj_opts *opts, pj_stream_t stream);
 
-/* Bytes of workspace a call with these sizes needs (L = 1 for the plain call). */
+/* Bytes of workspace a call with these sizes needs (L = 1: enough for both the
+ * plain call and a batched call holding one list). */
 size_t pj_list_rank_workspace_bytes(int64_t total_nodes, int64_t L, const pj_opts *opts);
+
+/*
+ * Batched list ranking with opts->use_graph = 1 captures the call's whole
+ * launch sequence once into a hipGraph (keyed by the buffers, sizes and
+ * options; the cache owns the workspace) and replays it with one
+ * hipGraphLaunch on later calls.  Not used together with opts->stats or with
+ * validate and no d_status.  The cache holds up to 8 graphs;
+ * pj_graph_cache_clear() frees them all (it synchronises the device).
+ */
+void pj_graph_cache_clear(void);
+
+/* ------------------------------------------------------------- autotuner */
+/*
+ * Times ruling-set parameter sets (first-level spacing 4..64, recursion
+ * spacing 4..16) on this input and records the fastest in the tune cache,
+ * keyed by (gfx arch, ceil(log2 nodes), ceil(log2 lists)).  Later list-ranking
+ * calls whose spacing / spacing_up / cutoff / max_walk are zero use the cached
+ * values for their size class; results never depend on them.  offsets == NULL
+ * tunes the single-list call on n nodes; otherwise offsets is the device
+ * table and h_offsets its host copy (required).  Writes the chosen options to
+ * *best and their mean time to *best_ms (either may be NULL).  Allocates a
+ * scratch output, runs ~60 solves and synchronises the stream.
+ */
+int pj_tune_list_rank(const int32_t *succ, const int64_t *offsets, int64_t L,
+                      const int64_t *h_offsets, int64_t n, pj_opts *best, float *best_ms,
+                      pj_stream_t stream);
+/* The tuned parameters for a size class, PJ_ENOTFOUND if none. */
+int pj_tune_lookup(int64_t n, int64_t L, pj_opts *out);
+/* Save / load the tune cache as text (one size class per line); the cache is
+ * also loaded from the file named by $PJ_TUNE_CACHE on first use. */
+int pj_tune_save(const char *path);
+int pj_tune_load(const char *path);
+void pj_tune_clear(void);
 
 /* ---------------------------------------------------- connected components */
 /*
@@ -167,7 +201,64 @@ int pj_connected_components_batched_ex(const int32_t *src, const int32_t *dst,
                                        int64_t G, int32_t *label, const pj_opts *opts,
                                        pj_stream_t stream);
 
+/* Bytes of workspace a components call needs (G = 1: enough for both the plain
+ * call and a batched call holding one graph). */
 size_t pj_cc_workspace_bytes(int64_t n, int64_t m, int64_t G, const pj_opts *opts);
+
+/* ----------------------------------------------------------------- serving */
+/*
+ * A request loop with continuous batching under an HBM budget.  Requests hold
+ * HOST arrays (pinned memory keeps the copies asynchronous) that must stay
+ * valid until the request is collected.  A scheduler thread admits waiting
+ * requests in arrival order into a tick while the tick's exact device
+ * footprint fits in the unused budget; each tick is one batched list ranking
+ * plus one batched components solve, run by one of max_inflight worker
+ * threads on its own stream, so ticks overlap on the device and requests that
+ * arrive meanwhile join the next tick as memory and a worker free up.
+ * Results are identical to a solve of the request alone.
+ */
+typedef struct pj_server pj_server;
+
+typedef struct pj_server_config {
+    size_t hbm_budget;      /* device bytes all in-flight ticks may hold (0 = 16 GiB) */
+    int32_t max_inflight;   /* ticks on the device at once, one worker and stream each (0 = 3) */
+    int32_t max_batch;      /* requests per tick (0 = 256) */
+    int32_t device;         /* HIP device (-1 = the calling thread's current device) */
+    int32_t reserved;
+    pj_opts opts;           /* solve options; workspace, d_status and stats are ignored */
+} pj_server_config;
+
+typedef struct pj_server_stats {
+    int64_t submitted, completed, failed;
+    int64_t ticks;           /* batched launches formed */
+    int64_t inflight_peak;   /* most ticks running at once */
+    int64_t budget_waits;    /* times the oldest request waited for memory */
+    size_t bytes_peak;       /* most device bytes held by ticks at once */
+    size_t bytes_in_use;
+    double p50_ms, p99_ms, mean_ms, max_ms; /* latency: submit to completion, completed requests */
+    double wall_s;           /* first submit to last completion */
+    double req_per_s;        /* completed requests per second of wall_s */
+    double items_per_s;      /* list nodes + graph pairs per second of wall_s */
+} pj_server_stats;
+
+int pj_server_create(const pj_server_config *cfg, pj_server **out);
+/* Submit a request; PJ_EBUDGET if it alone exceeds the whole budget,
+ * PJ_ESHUTDOWN after destroy began.  *id identifies it. */
+int pj_server_submit_list_rank(pj_server *srv, const int32_t *h_succ, int64_t n, int32_t *h_rank,
+                               uint64_t *id);
+int pj_server_submit_cc(pj_server *srv, const int32_t *h_src, const int32_t *h_dst, int64_t n,
+                        int64_t m, int32_t *h_label, uint64_t *id);
+/* PJ_OK once finished (the request's result code goes to *status and its
+ * latency to *latency_ms; the id is then forgotten), PJ_EBUSY while pending,
+ * PJ_ENOTFOUND for an unknown id.  wait blocks up to timeout_us (< 0: forever). */
+int pj_server_poll(pj_server *srv, uint64_t id, int32_t *status, double *latency_ms);
+int pj_server_wait(pj_server *srv, uint64_t id, int32_t *status, double *latency_ms,
+                   int64_t timeout_us);
+/* Block until every submitted request has finished. */
+int pj_server_drain(pj_server *srv);
+int pj_server_get_stats(pj_server *srv, pj_server_stats *out);
+/* Finish all submitted requests, stop the threads and free the server. */
+int pj_server_destroy(pj_server *srv);
 
 #ifdef __cplusplus
 }

@@ -79,6 +79,40 @@ class PjOpts(ctypes.Structure):
     ]
 
 
+class PjServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("hbm_budget", ctypes.c_size_t),
+        ("max_inflight", ctypes.c_int32),
+        ("max_batch", ctypes.c_int32),
+        ("device", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
+        ("opts", PjOpts),
+    ]
+
+
+class PjServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("ticks", ctypes.c_int64),
+        ("inflight_peak", ctypes.c_int64),
+        ("budget_waits", ctypes.c_int64),
+        ("bytes_peak", ctypes.c_size_t),
+        ("bytes_in_use", ctypes.c_size_t),
+        ("p50_ms", ctypes.c_double),
+        ("p99_ms", ctypes.c_double),
+        ("mean_ms", ctypes.c_double),
+        ("max_ms", ctypes.c_double),
+        ("wall_s", ctypes.c_double),
+        ("req_per_s", ctypes.c_double),
+        ("items_per_s", ctypes.c_double),
+    ]
+
+    def to_dict(self):
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
 class PjError(RuntimeError):
     def __init__(self, code, where=""):
         lib = load()
@@ -109,6 +143,20 @@ SIGNATURES = [
     ("pj_connected_components_batched_ex", ctypes.c_int,
      [_VP, _VP, _VP, _VP, _I64, _VP, _VP, _VP]),
     ("pj_cc_workspace_bytes", _SZ, [_I64, _I64, _I64, _VP]),
+    ("pj_graph_cache_clear", None, []),
+    ("pj_tune_list_rank", ctypes.c_int, [_VP, _VP, _I64, _VP, _I64, _VP, _VP, _VP]),
+    ("pj_tune_lookup", ctypes.c_int, [_I64, _I64, _VP]),
+    ("pj_tune_save", ctypes.c_int, [ctypes.c_char_p]),
+    ("pj_tune_load", ctypes.c_int, [ctypes.c_char_p]),
+    ("pj_tune_clear", None, []),
+    ("pj_server_create", ctypes.c_int, [_VP, _VP]),
+    ("pj_server_submit_list_rank", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP]),
+    ("pj_server_submit_cc", ctypes.c_int, [_VP, _VP, _VP, _I64, _I64, _VP, _VP]),
+    ("pj_server_poll", ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP]),
+    ("pj_server_wait", ctypes.c_int, [_VP, ctypes.c_uint64, _VP, _VP, _I64]),
+    ("pj_server_drain", ctypes.c_int, [_VP]),
+    ("pj_server_get_stats", ctypes.c_int, [_VP, _VP]),
+    ("pj_server_destroy", ctypes.c_int, [_VP]),
 ]
 
 

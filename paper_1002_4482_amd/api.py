@@ -146,3 +146,50 @@ def connected_components_batched(src, dst, vtx_off, edge_off, label=None, *, h_v
         _stream_ptr(stream))
     _check(rc, "pj_connected_components_batched")
     return (label, st.to_dict()) if return_stats else label
+
+
+def tune_list_rank(succ, offsets=None, *, h_offsets=None, stream=None):
+    """Autotune the ruling-set parameters on this input (single list when
+    `offsets` is None).  Returns (best parameters dict, mean ms)."""
+    succ = _dev_i32(succ, "succ")
+    best = PjOpts()
+    ms = ctypes.c_float(0.0)
+    lib = _lib.load()
+    if offsets is None:
+        rc = lib.pj_tune_list_rank(_ptr(succ), None, 1, None, succ.numel(), ctypes.byref(best),
+                                   ctypes.byref(ms), _stream_ptr(stream))
+    else:
+        offsets = _dev_i64(offsets, "offsets")
+        if h_offsets is None:
+            h_offsets = offsets.cpu().numpy()
+        rc = lib.pj_tune_list_rank(_ptr(succ), _ptr(offsets), offsets.numel() - 1,
+                                   ctypes.c_void_p(h_offsets.ctypes.data), 0, ctypes.byref(best),
+                                   ctypes.byref(ms), _stream_ptr(stream))
+    _check(rc, "pj_tune_list_rank")
+    return ({"spacing": best.spacing, "spacing_up": best.spacing_up, "cutoff": best.cutoff,
+             "max_walk": best.max_walk}, float(ms.value))
+
+
+def tune_lookup(n, L=1):
+    o = PjOpts()
+    rc = _lib.load().pj_tune_lookup(n, L, ctypes.byref(o))
+    if rc != _lib.PJ_OK:
+        return None
+    return {"spacing": o.spacing, "spacing_up": o.spacing_up, "cutoff": o.cutoff,
+            "max_walk": o.max_walk}
+
+
+def tune_save(path):
+    _check(_lib.load().pj_tune_save(str(path).encode()), "pj_tune_save")
+
+
+def tune_load(path):
+    _check(_lib.load().pj_tune_load(str(path).encode()), "pj_tune_load")
+
+
+def tune_clear():
+    _lib.load().pj_tune_clear()
+
+
+def graph_cache_clear():
+    _lib.load().pj_graph_cache_clear()

@@ -278,12 +278,18 @@ __global__ void __launch_bounds__(256) canon_label(int32_t* D, const int32_t* __
 // Batched: rewrite local pairs as global vertex ids (graph g's vertices start
 // at voff[g]).  A pair whose ends leave its graph is made out of range so the
 // rounds skip it and report it.
+__global__ void gerr_clear(int32_t* gerr, int G) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x)
+    gerr[g] = 0;
+}
+
 __global__ void __launch_bounds__(256) cc_globalise(const int32_t* __restrict__ src,
                                                     const int32_t* __restrict__ dst,
                                                     const int64_t* __restrict__ voff,
                                                     const int64_t* __restrict__ eoff, int G,
                                                     int64_t m, int32_t* __restrict__ gsrc,
-                                                    int32_t* __restrict__ gdst) {
+                                                    int32_t* __restrict__ gdst,
+                                                    int32_t* __restrict__ gerr) {
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int g = find_instance(eoff, G, e);
@@ -293,16 +299,22 @@ __global__ void __launch_bounds__(256) cc_globalise(const int32_t* __restrict__ 
     const bool ok = (unsigned)u < (uint64_t)size && (unsigned)v < (uint64_t)size;
     gsrc[e] = ok ? (int)(base + u) : -1;
     gdst[e] = ok ? (int)(base + v) : -1;
+    if (!ok) gerr[g] = 1;
   }
 }
 
+// Out-of-range pairs are charged to their own graph when the batch records
+// them per graph (gerr); non-convergence concerns the whole solve.
 __global__ void cc_status(const CcCtl* ctl, const int32_t* w, int max_rounds, int G,
-                          int32_t* status) {
-  int st = PJ_OK;
-  if (ctl->err & kErrRange) st = PJ_EINVAL;
-  else if (ctl->rounds >= max_rounds && w[max_rounds] != 0) st = PJ_ENOCONV;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x)
+                          const int32_t* gerr, int32_t* status) {
+  const bool noconv = ctl->rounds >= max_rounds && w[max_rounds] != 0;
+  const bool range = (ctl->err & kErrRange) != 0;
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
+    int st = PJ_OK;
+    if (gerr ? gerr[g] != 0 : range) st = PJ_EINVAL;
+    else if (noconv) st = PJ_ENOCONV;
     status[g] = st;
+  }
 }
 
 inline int grid_for(int64_t n, int block, int cap) {
@@ -327,6 +339,7 @@ struct CcBuffers {
   unsigned long long* mcount = nullptr;  // surviving pairs after step 2 of each round
   int32_t* gsrc = nullptr;
   int32_t* gdst = nullptr;
+  int32_t* gerr = nullptr;               // batched: per-graph out-of-range flag
   int32_t* es[2] = {};                   // compacted pair lists (ping-pong)
   int32_t* ed[2] = {};
   int2* cache = nullptr;                 // (D[i], D[j]) seen by step 2
@@ -355,6 +368,7 @@ size_t cc_carve(int64_t n, int64_t m, int64_t G, bool batched, bool want_status,
   if (batched) {
     take(b->gsrc, (size_t)std::max<int64_t>(m, 1));
     take(b->gdst, (size_t)std::max<int64_t>(m, 1));
+    take(b->gerr, (size_t)std::max<int64_t>(G, 1));
   }
   if (want_status) take(b->status_tmp, (size_t)std::max<int64_t>(G, 1));
   return bytes;
@@ -399,11 +413,15 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
 
   const int32_t* es = src;
   const int32_t* ed = dst;
-  if (batched && m > 0) {
-    hipLaunchKernelGGL(cc_globalise, dim3(grid_for(m, 256, gcap)), dim3(256), 0, stream, src, dst,
-                       d_voff, d_eoff, (int)G, m, b.gsrc, b.gdst);
-    es = b.gsrc;
-    ed = b.gdst;
+  if (batched) {
+    hipLaunchKernelGGL(gerr_clear, dim3(grid_for(G, 256, 1024)), dim3(256), 0, stream, b.gerr,
+                       (int)G);
+    if (m > 0) {
+      hipLaunchKernelGGL(cc_globalise, dim3(grid_for(m, 256, gcap)), dim3(256), 0, stream, src,
+                         dst, d_voff, d_eoff, (int)G, m, b.gsrc, b.gdst, b.gerr);
+      es = b.gsrc;
+      ed = b.gdst;
+    }
   }
   hipLaunchKernelGGL(sv_init, dim3(gv), dim3(256), 0, stream, D, b.NS, b.Q, ni, b.w, b.mcount,
                      wlen, b.ctl);
@@ -458,7 +476,7 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
   }
   if (status && G > 0) {
     hipLaunchKernelGGL(cc_status, dim3(grid_for(G, 256, 1024)), dim3(256), 0, stream, b.ctl, b.w,
-                       max_rounds, (int)G, status);
+                       max_rounds, (int)G, batched ? b.gerr : nullptr, status);
     PJ_HIP(hipGetLastError());
   }
   if (want_status && G > 0) {
@@ -539,7 +557,9 @@ int pj_connected_components_batched(const int32_t* src, const int32_t* dst,
 
 size_t pj_cc_workspace_bytes(int64_t n, int64_t m, int64_t G, const pj_opts* opts) {
   if (n < 0 || m < 0 || G < 1) return 0;
-  return pj::cc_workspace(n, m, G, opts, G > 1);
+  // one graph may go through either entry point: size for the larger layout
+  const size_t batched = pj::cc_workspace(n, m, G, opts, true);
+  return G > 1 ? batched : std::max(batched, pj::cc_workspace(n, m, G, opts, false));
 }
 
 }  // extern "C"

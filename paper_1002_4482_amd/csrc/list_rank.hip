@@ -33,7 +33,7 @@
 namespace pj {
 namespace {
 
-constexpr int kMaxCutoff = 8192;
+constexpr int kMaxCutoff = 16384;
 constexpr int kBaseThreads = 1024;
 constexpr int kPerThread = kMaxCutoff / kBaseThreads;
 
@@ -953,6 +953,8 @@ size_t carve(const Plan& p, int64_t L, bool single, bool validate, bool want_sta
   return bytes;
 }
 
+}  // namespace
+
 int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,
                    int64_t n_single, int32_t* rank, const pj_opts* user, hipStream_t stream) {
   const bool single = d_off == nullptr;
@@ -996,6 +998,16 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
   const bool want_status = o.validate && !o.d_status;
   if (n0 == 0 && !o.d_status) return PJ_OK;
 
+  {  // ruling-set parameters left at zero come from the tune cache, if tuned
+    pj_opts raw;
+    pj_opts_init(&raw);
+    if (user) raw = *user;
+    apply_tuned(raw, n0, L);
+    o.spacing = raw.spacing > 0 ? raw.spacing : o.spacing;
+    o.spacing_up = raw.spacing_up > 0 ? raw.spacing_up : o.spacing_up;
+    o.cutoff = raw.cutoff > 0 ? std::min(std::max(raw.cutoff, 64), 16384) : o.cutoff;
+    o.max_walk = raw.max_walk > 0 ? std::max(raw.max_walk, 16) : o.max_walk;
+  }
   Plan p = make_plan(n0, L, max_size, o);
   Buffers b;
   const size_t need = carve(p, L, single, o.validate != 0, want_status, nullptr, &b);
@@ -1210,10 +1222,12 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
   return result;
 }
 
-}  // namespace
-
 size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single) {
-  pj_opts o = resolved_opts(user);
+  pj_opts raw;
+  pj_opts_init(&raw);
+  if (user) raw = *user;
+  apply_tuned(raw, n0, L);
+  pj_opts o = resolved_opts(&raw);
   Plan p = make_plan(n0, L, n0, o);
   Buffers b;
   return carve(p, L, single, o.validate != 0, o.validate && !o.d_status, nullptr, &b);
@@ -1236,6 +1250,22 @@ int pj_list_rank(const int32_t* succ, int64_t n, int32_t* rank, pj_stream_t stre
 int pj_list_rank_batched_ex(const int32_t* succ, const int64_t* offsets, int64_t L,
                             int32_t* rank, const pj_opts* opts, pj_stream_t stream) {
   if (!offsets || L < 0) return PJ_EINVAL;
+  if (opts && opts->use_graph && !opts->stats && !(opts->validate && !opts->d_status) && L > 0) {
+    std::vector<int64_t> hbuf;
+    const int64_t* ho = opts->h_offsets;
+    if (!ho) {
+      hbuf.resize((size_t)L + 1);
+      PJ_HIP(hipMemcpyAsync(hbuf.data(), offsets, sizeof(int64_t) * (L + 1),
+                            hipMemcpyDeviceToHost, (hipStream_t)stream));
+      PJ_HIP(hipStreamSynchronize((hipStream_t)stream));
+      ho = hbuf.data();
+    }
+    if (ho[0] != 0 || ho[L] < 0 || ho[L] >= INT32_MAX) return PJ_EINVAL;
+    for (int64_t l = 0; l < L; ++l)
+      if (ho[l + 1] < ho[l]) return PJ_EINVAL;
+    if (ho[L] > 0 && (!succ || !rank || (const void*)succ == (const void*)rank)) return PJ_EINVAL;
+    return pj::graph_batched(succ, offsets, L, ho, rank, *opts, (hipStream_t)stream);
+  }
   return pj::list_rank_impl(succ, offsets, L, opts ? opts->h_offsets : nullptr, 0, rank, opts,
                             (hipStream_t)stream);
 }
@@ -1247,7 +1277,10 @@ int pj_list_rank_batched(const int32_t* succ, const int64_t* offsets, int64_t L,
 
 size_t pj_list_rank_workspace_bytes(int64_t total_nodes, int64_t L, const pj_opts* opts) {
   if (total_nodes < 0 || L < 1) return 0;
-  return pj::list_rank_workspace(total_nodes, L, opts, L == 1);
+  // one list may go through either entry point: size for the larger layout
+  const size_t batched = pj::list_rank_workspace(total_nodes, L, opts, false);
+  return L > 1 ? batched
+               : std::max(batched, pj::list_rank_workspace(total_nodes, L, opts, true));
 }
 
 }  // extern "C"

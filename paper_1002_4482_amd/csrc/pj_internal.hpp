@@ -99,6 +99,20 @@ struct PhaseTimer {
 // Resolve option defaults.
 pj_opts resolved_opts(const pj_opts* in);
 
+// List ranking entry shared by the plain, batched, graph and tuning paths.
+// d_off == nullptr means one list of n_single nodes.
+int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,
+                   int64_t n_single, int32_t* rank, const pj_opts* user, hipStream_t stream);
+size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single);
+
+// Tuned ruling-set parameters for a problem of n0 nodes in L lists, if the
+// tune cache holds an entry for its size class; fills the zero fields of o.
+void apply_tuned(pj_opts& o, int64_t n0, int64_t L);
+
+// Batched list ranking through the captured-graph cache (h_off required).
+int graph_batched(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,
+                  int32_t* rank, const pj_opts& user, hipStream_t stream);
+
 // ---------------------------------------------------------- device helpers
 // 32-bit finaliser of MurmurHash3 (Appleby), used as a counter-based hash to
 // place one splitter per block of node ids.

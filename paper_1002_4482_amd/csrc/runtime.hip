@@ -152,9 +152,9 @@ pj_opts resolved_opts(const pj_opts* in) {
   if (o.block > 1024) o.block = 1024;
   if (o.spacing <= 0) o.spacing = 16;
   if (o.spacing_up <= 0) o.spacing_up = 8;
-  if (o.cutoff <= 0) o.cutoff = 8192;
+  if (o.cutoff <= 0) o.cutoff = 16384;
   if (o.cutoff < 64) o.cutoff = 64;
-  if (o.cutoff > 8192) o.cutoff = 8192;
+  if (o.cutoff > 16384) o.cutoff = 16384;
   if (o.max_walk <= 0) o.max_walk = 1024;
   if (o.max_walk < 16) o.max_walk = 16;
   if (o.rounds_per_check <= 0) o.rounds_per_check = 2;

@@ -63,7 +63,10 @@ def test_host_only_calls(lib):
     L.pj_opts_init(ctypes.byref(o))
     assert o.algo == 0 and o.seed != 0
     # workspace sizing is host arithmetic
-    assert L.pj_list_rank_workspace_bytes(1 << 20, 1, None) > 8 * (1 << 20)
+    plain = L.pj_list_rank_workspace_bytes(1 << 20, 1, None)
+    assert 0 < plain < 64 * (1 << 20)
+    o.validate = 1
+    assert L.pj_list_rank_workspace_bytes(1 << 20, 1, ctypes.byref(o)) >= plain + 4 * (1 << 20)
     assert L.pj_cc_workspace_bytes(1 << 20, 1 << 22, 1, None) >= 8 * (1 << 20)
 
 
@@ -75,12 +78,13 @@ def _c_sizeof(struct, field=None):
 
 def test_struct_layout_matches_ctypes(tmp_path):
     from paper_1002_4482_amd import _lib
-    checks = [("pj_opts", None, ctypes.sizeof(_lib.PjOpts)),
-              ("pj_stats", None, ctypes.sizeof(_lib.PjStats))]
-    for f, _ in _lib.PjOpts._fields_:
-        checks.append(("pj_opts", f, getattr(_lib.PjOpts, f).offset))
-    for f, _ in _lib.PjStats._fields_:
-        checks.append(("pj_stats", f, getattr(_lib.PjStats, f).offset))
+    checks = []
+    for cname, cls in (("pj_opts", _lib.PjOpts), ("pj_stats", _lib.PjStats),
+                       ("pj_server_config", _lib.PjServerConfig),
+                       ("pj_server_stats", _lib.PjServerStats)):
+        checks.append((cname, None, ctypes.sizeof(cls)))
+        for f, _ in cls._fields_:
+            checks.append((cname, f, getattr(cls, f).offset))
     for i, (s, f, want) in enumerate(checks):
         c = tmp_path / f"t{i}.c"
         c.write_text(_c_sizeof(s, f))

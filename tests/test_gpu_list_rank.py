@@ -231,3 +231,82 @@ def test_batched_equals_per_list(pj):
         one = pj.list_rank(d_succ[off[i]:off[i + 1]].clone())
         torch.cuda.synchronize()
         assert torch.equal(one, got[off[i]:off[i + 1]])
+
+
+# ----------------------------------------------------------- graph + tuning
+def test_graph_replay_matches_eager_every_time(pj):
+    """The captured batched graph, replayed several times with eager work and
+    syncs in between, gives the eager result each time."""
+    succ, off = batched_case(300, 3, 16, 5)
+    d_succ, d_off = dev(succ), dev(off)
+    want = oracle.list_rank_batched(succ, off)[1]
+    eager = pj.list_rank_batched(d_succ, d_off, h_offsets=off)
+    torch.cuda.synchronize()
+    assert np.array_equal(eager.cpu().numpy(), want)
+    out = torch.empty_like(d_succ)
+    for rep in range(4):
+        out.fill_(-7)
+        pj.list_rank_batched(d_succ, d_off, out, h_offsets=off, use_graph=True)
+        torch.cuda.synchronize()
+        assert torch.equal(out, eager), rep
+        # unrelated eager work between replays
+        pj.list_rank(d_succ[off[0]:off[1]].clone())
+        torch.cuda.synchronize()
+    # new contents, same buffers and sizes: the replay reads the new input
+    succ2, _ = batched_case(300, 3, 16, 5)
+    rng = np.random.default_rng(1)
+    for i in range(300):
+        seg = slice(off[i], off[i + 1])
+        perm = rng.permutation(off[i + 1] - off[i]).astype(np.int32)
+        s = np.empty_like(perm)
+        if len(perm):
+            s[perm[:-1]] = perm[1:]
+            s[perm[-1]] = -1
+        succ2[seg] = s
+    d_succ.copy_(dev(succ2))
+    pj.list_rank_batched(d_succ, d_off, out, h_offsets=off, use_graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.list_rank_batched(succ2, off)[1])
+    pj.graph_cache_clear()
+
+
+def test_graph_replay_single_large_list(pj):
+    n = 3_000_017
+    succ = W.random_list(n, 12)
+    off = np.array([0, n], dtype=np.int64)
+    want = oracle.list_rank(succ)
+    d_succ, d_off = dev(succ), dev(off)
+    out = torch.empty_like(d_succ)
+    for _ in range(3):
+        out.zero_()
+        pj.list_rank_batched(d_succ, d_off, out, h_offsets=off, use_graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want)
+    pj.graph_cache_clear()
+
+
+def test_autotune_picks_parameters_and_keeps_results(pj, tmp_path):
+    n = 1 << 20
+    succ = W.random_list(n, 21)
+    d_succ = dev(succ)
+    pj.tune_clear()
+    best, ms = pj.tune_list_rank(d_succ)
+    assert best["spacing"] in (4, 8, 16, 32, 64) and ms > 0
+    assert pj.tune_lookup(n) == best
+    got = pj.list_rank(d_succ)   # uses the tuned parameters
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.list_rank(succ))
+    path = tmp_path / "tune.txt"
+    pj.tune_save(path)
+    pj.tune_clear()
+    assert pj.tune_lookup(n) is None
+    pj.tune_load(path)
+    assert pj.tune_lookup(n) == best
+    # batched tuning
+    bs, boff = batched_case(200, 6, 14, 3)
+    best_b, _ = pj.tune_list_rank(dev(bs), dev(boff), h_offsets=boff)
+    assert pj.tune_lookup(int(boff[-1]), 200) == best_b
+    got = pj.list_rank_batched(dev(bs), dev(boff), h_offsets=boff)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.list_rank_batched(bs, boff)[1])
+    pj.tune_clear()

@@ -1,0 +1,158 @@
+"""The serving loop (pj_server_*): continuous batching under an HBM budget.
+
+Every response is checked against the oracle; a request's result is the same
+alone and in the mix (tolerance 0); a small budget forces admission waits
+without ever exceeding the budget; a malformed request fails alone.
+"""
+
+import threading
+import time
+
+import numpy as np
+import pytest
+
+import oracle
+import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def serve():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_1002_4482_amd as pj
+    from paper_1002_4482_amd import serve as S
+    pj.load()
+    return S
+
+
+def make_mix(count, seed, lr_exp=(0, 17), cc_exp=(0, 14)):
+    rng = np.random.default_rng(seed)
+    reqs = []
+    for i in range(count):
+        if rng.random() < 0.7:
+            n = int(np.floor(2 ** rng.uniform(*lr_exp)))
+            reqs.append(("lr", W.random_list(n, seed * 1000 + i)))
+        else:
+            n = int(np.floor(2 ** rng.uniform(*cc_exp)))
+            m = int(round(n * rng.uniform(2, 16) / 2))
+            src, dst = W.random_graph(n, m, seed * 1000 + i)
+            reqs.append(("cc", (src, dst, n)))
+    return reqs
+
+
+def expected(req):
+    kind, data = req
+    if kind == "lr":
+        return oracle.list_rank(data)
+    src, dst, n = data
+    return oracle.connected_components(src, dst, n)
+
+
+def submit(srv, req):
+    kind, data = req
+    if kind == "lr":
+        return srv.submit_list_rank(data)
+    src, dst, n = data
+    return srv.submit_cc(src, dst, n)
+
+
+def test_mix_matches_oracle_and_alone(serve):
+    reqs = make_mix(80, 1)
+    reqs.insert(5, ("lr", np.empty(0, np.int32)))
+    reqs.insert(9, ("cc", (np.empty(0, np.int32), np.empty(0, np.int32), 17)))
+    with serve.Server(hbm_budget=4 << 30, max_inflight=3, max_batch=16) as srv:
+        ids = [submit(srv, r) for r in reqs]
+        mixed = {}
+        for rid, r in zip(ids, reqs):
+            st, lat, out = srv.wait(rid, timeout_s=60)
+            assert st == 0
+            assert lat >= 0
+            assert np.array_equal(out, expected(r))
+            mixed[rid] = out.copy()
+        s = srv.stats()
+        assert s["completed"] == len(reqs) and s["failed"] == 0
+        assert s["ticks"] >= len(reqs) // 16
+        assert 0 < s["p50_ms"] <= s["p99_ms"] <= s["max_ms"]
+    # the same requests, each alone on a fresh server, give identical results
+    with serve.Server(hbm_budget=4 << 30, max_inflight=1, max_batch=1) as solo:
+        for rid, r in list(zip(ids, reqs))[::7]:
+            st, _, out = solo.wait(submit(solo, r), timeout_s=60)
+            assert st == 0
+            assert np.array_equal(out, mixed[rid])
+
+
+def test_small_budget_waits_and_never_exceeds(serve):
+    reqs = [("lr", W.random_list(1 << 18, 100 + i)) for i in range(12)]
+    reqs += [("cc", (*W.random_graph(1 << 16, 1 << 18, 200 + i), 1 << 16)) for i in range(6)]
+    budget = 24 << 20
+    with serve.Server(hbm_budget=budget, max_inflight=3, max_batch=64) as srv:
+        ids = [submit(srv, r) for r in reqs]
+        for rid, r in zip(ids, reqs):
+            st, _, out = srv.wait(rid, timeout_s=60)
+            assert st == 0
+            assert np.array_equal(out, expected(r))
+        s = srv.stats()
+        assert s["bytes_peak"] <= budget
+        assert s["budget_waits"] > 0
+        assert s["bytes_in_use"] == 0
+
+
+def test_request_larger_than_budget_is_refused(serve):
+    with serve.Server(hbm_budget=1 << 20) as srv:
+        with pytest.raises(Exception) as ei:
+            srv.submit_list_rank(W.random_list(1 << 20, 1))
+        assert getattr(ei.value, "code", None) == -6
+        # a small one still goes through
+        st, _, out = srv.wait(srv.submit_list_rank(W.random_list(1000, 2)), timeout_s=30)
+        assert st == 0 and np.array_equal(out, oracle.list_rank(W.random_list(1000, 2)))
+
+
+def test_malformed_requests_fail_alone(serve):
+    good = make_mix(20, 3)
+    bad_list = W.random_list(5000, 9).copy()
+    bad_list[np.nonzero(bad_list != -1)[0][10]] = -1          # two tails
+    bad_graph = W.random_graph(300, 900, 4)
+    bad_graph = (bad_graph[0], bad_graph[1].copy(), 300)
+    bad_graph[1][5] = 999                                     # end outside the graph
+    reqs = good[:10] + [("lr", bad_list)] + good[10:15] + [("cc", bad_graph)] + good[15:]
+    with serve.Server(hbm_budget=4 << 30, max_inflight=2, max_batch=64) as srv:
+        ids = [submit(srv, r) for r in reqs]
+        for rid, r in zip(ids, reqs):
+            st, _, out = srv.wait(rid, timeout_s=60)
+            if r[1] is bad_list:
+                assert st == oracle.EBADLIST
+            elif r[1] is bad_graph:
+                assert st == oracle.EINVAL
+            else:
+                assert st == 0
+                assert np.array_equal(out, expected(r))
+
+
+def test_arrivals_while_busy_overlap(serve):
+    """Requests arriving while ticks run are admitted as workers free up, and
+    several ticks are on the device at once."""
+    reqs = make_mix(120, 5, lr_exp=(10, 19), cc_exp=(10, 16))
+    with serve.Server(hbm_budget=8 << 30, max_inflight=3, max_batch=8) as srv:
+        ids = [None] * len(reqs)
+
+        def producer():
+            rng = np.random.default_rng(0)
+            for i, r in enumerate(reqs):
+                ids[i] = submit(srv, r)
+                time.sleep(float(rng.exponential(0.0005)))
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        srv.drain()
+        for rid, r in zip(ids, reqs):
+            st, _, out = srv.poll(rid)
+            assert st == 0
+            assert np.array_equal(out, expected(r))
+        s = srv.stats()
+        assert s["completed"] == len(reqs)
+        assert s["ticks"] > 1
+        assert s["inflight_peak"] >= 2
