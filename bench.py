@@ -325,14 +325,123 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
     def batched():
         pj.list_rank_batched(dbs, dboff, dbr, h_offsets=boff)
 
+    def graphed():
+        pj.list_rank_batched(dbs, dboff, dbr, h_offsets=boff, use_graph=True)
+
     ms_b = timed(torch, batched, steps, 1)
     ms_p = timed(torch, plain, 2, 1)
+    ms_g = timed(torch, graphed, steps, 1)
+    # tuned parameters for this size class, then the graph replay again
+    best, _ = pj.tune_list_rank(dbs, dboff, h_offsets=boff)
+    pj.graph_cache_clear()
+    ms_t = timed(torch, graphed, steps, 1)
+    pj.graph_cache_clear()
     ex["c4_total_nodes"] = total
     ex["c4_batched_ms"] = round(ms_b, 3)
+    ex["c4_batched_graph_ms"] = round(ms_g, 3)
+    ex["c4_batched_graph_tuned_ms"] = round(ms_t, 3)
+    ex["c4_tuned"] = best
     ex["c4_plain_ms"] = round(ms_p, 3)
-    ex["c4_batched_nodes_per_s"] = round(total / (ms_b * 1e-3), 1)
-    ex["c4_speedup_batched_vs_plain"] = round(ms_p / ms_b, 3)
-    log(f"batched {ms_b:.3f} ms plain {ms_p:.3f} ms")
+    ex["c4_batched_nodes_per_s"] = round(total / (min(ms_b, ms_g, ms_t) * 1e-3), 1)
+    ex["c4_speedup_batched_vs_plain"] = round(ms_p / min(ms_b, ms_g, ms_t), 3)
+    log(f"batched {ms_b:.3f} ms graph {ms_g:.3f} ms tuned {ms_t:.3f} ms {best} "
+        f"plain {ms_p:.3f} ms")
+    del dbs, dboff, dbr, views
+    pj.tune_clear()
+    ex.update(run_serving(torch, pj, args))
+    return ex
+
+
+def serving_pool(seed, lists=24, graphs=12):
+    """Distinct inputs drawn from the serving mix, with their oracle results."""
+    import oracle
+    rng = np.random.default_rng(seed)
+    pool = {"lr": [], "cc": []}
+    for i in range(lists):
+        n = int(np.floor(2 ** rng.uniform(10, 24)))
+        s = W.random_list(n, seed + i)
+        pool["lr"].append((s, oracle.list_rank(s)))
+    for i in range(graphs):
+        n = int(np.floor(2 ** rng.uniform(10, 22)))
+        m = int(round(n * rng.uniform(2, 16) / 2))
+        src, dst = W.random_graph(n, m, seed + 100 + i)
+        pool["cc"].append((src, dst, n, oracle.connected_components(src, dst, n)))
+    return pool
+
+
+def serve_run(torch, S, pool, count, rate, seed, budget, check=True):
+    """Submit `count` requests (70% lists) with Poisson arrivals at `rate`
+    per second (rate None: all at once); returns the server's stats."""
+    import threading
+    rng = np.random.default_rng(seed)
+    picks = [("lr", int(rng.integers(len(pool["lr"])))) if rng.random() < 0.7 else
+             ("cc", int(rng.integers(len(pool["cc"])))) for _ in range(count)]
+    gaps = rng.exponential(1.0 / rate, count) if rate else np.zeros(count)
+    ids = [None] * count
+    with S.Server(hbm_budget=budget, max_inflight=3, max_batch=64) as srv:
+        def producer():
+            t0 = time.perf_counter()
+            due = 0.0
+            for i, (kind, j) in enumerate(picks):
+                due += gaps[i]
+                delay = t0 + due - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                if kind == "lr":
+                    ids[i] = srv.submit_list_rank(pool["lr"][j][0])
+                else:
+                    src, dst, n, _ = pool["cc"][j]
+                    ids[i] = srv.submit_cc(src, dst, n)
+
+        th = threading.Thread(target=producer)
+        th.start()
+        th.join()
+        srv.drain()
+        bad = []
+        for i, (rid, (kind, j)) in enumerate(zip(ids, picks)):
+            st, _, out = srv.wait(rid)
+            want = pool["lr"][j][1] if kind == "lr" else pool["cc"][j][3]
+            wrong = int((out != want).sum()) if check and st == 0 else 0
+            if st != 0 or wrong:
+                bad.append({"request": i, "kind": kind, "input": j, "status": int(st),
+                            "size": int(len(want)), "wrong": wrong})
+        stats = srv.stats()
+    for b in bad:
+        log(f"serving mismatch {b}")
+    stats["mismatches"] = len(bad)
+    return stats
+
+
+def run_serving(torch, pj, args):
+    from paper_1002_4482_amd import serve as S
+    log("serving: building the request pool")
+    pool = serving_pool(W.SEED_BASE + 5)
+    # pinned host copies keep the server's copies asynchronous
+    pool["lr"] = [(torch.from_numpy(s).pin_memory(), r) for s, r in pool["lr"]]
+    pool["cc"] = [(torch.from_numpy(a).pin_memory(), torch.from_numpy(b).pin_memory(), n, r)
+                  for a, b, n, r in pool["cc"]]
+    ex = {}
+    serve_run(torch, S, pool, 40, None, 1, 16 << 30)  # warm-up
+    sat = serve_run(torch, S, pool, 300, None, 2, 16 << 30)
+    lam = 0.75 * sat["req_per_s"]
+    log(f"serving saturation {sat['req_per_s']:.1f} req/s; open loop at {lam:.1f} req/s")
+    run = serve_run(torch, S, pool, 600, lam, 3, 16 << 30)
+    small = serve_run(torch, S, pool, 200, lam, 4, 512 << 20)
+    ex["c5_saturation_req_per_s"] = round(sat["req_per_s"], 1)
+    ex["c5_rate_req_per_s"] = round(lam, 1)
+    for tag, st in (("c5", run), ("c5_budget512MiB", small)):
+        ex[f"{tag}_p50_ms"] = round(st["p50_ms"], 3)
+        ex[f"{tag}_p99_ms"] = round(st["p99_ms"], 3)
+        ex[f"{tag}_req_per_s"] = round(st["req_per_s"], 1)
+        ex[f"{tag}_items_per_s"] = round(st["items_per_s"], 1)
+        ex[f"{tag}_completed"] = st["completed"]
+        ex[f"{tag}_mismatches"] = st["mismatches"]
+        ex[f"{tag}_ticks"] = st["ticks"]
+        ex[f"{tag}_inflight_peak"] = st["inflight_peak"]
+        ex[f"{tag}_budget_waits"] = st["budget_waits"]
+        ex[f"{tag}_bytes_peak"] = st["bytes_peak"]
+        log(f"{tag}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
+            f"{st['req_per_s']:.1f} req/s mismatches {st['mismatches']}")
     return ex
 
 

@@ -20,10 +20,10 @@
 //                         concurrent writes); the solve ends after the first
 //                         round with w[s] == 0.
 // Each pair is processed in both orientations by the thread that reads it.
-// Step 2 also drops every pair whose two ends already have the same parent
-// (they lie in one tree, and trees only ever merge), compacting the survivors
-// into the list the next round reads, together with the (D[i], D[j]) values it
-// read, which step 3 of the same round uses instead of gathering them again.
+// Before step 2 a compaction kernel drops every pair whose two ends already
+// have the same parent (they lie in one tree, and trees only ever merge) and
+// writes the survivors, with their two parents, for steps 2 and 3 and for
+// the next round.
 // Concurrent writes to one root land in arbitrary order; every outcome is
 // one the arbitrary-CRCW algorithm allows: step 2 only hooks star roots onto
 // strictly smaller ids, step 3 only hooks stars that no step-2 hook touched,
@@ -95,35 +95,39 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
   if (__ballot(changed) && lane_id() == 0) w[s] = 1;
 }
 
-// Step 2, with compaction of the pairs that can still matter.  A workgroup
-// handles chunks of kHookPer * 256 pairs and reserves room for its survivors
-// with one atomic per chunk.
-constexpr int kHookPer = 8;
-constexpr int kHookWaves = 256 / kWave;
+// Pair compaction, a kernel of its own between steps 1b and 2: keeps the
+// pairs whose ends have different parents (a pair whose ends share a parent
+// lies inside one tree for good, since trees only merge), together with the
+// two parents, which steps 2 and 3 of the round then read coalesced instead
+// of gathering.  D is not written while this kernel runs; that matters:
+// step 2 may hook one root twice (arbitrary winner), and a compaction decision
+// taken between those two writes could drop a pair that the second write
+// separates.  A workgroup reserves room for the survivors of each chunk of
+// kCompactPer * 256 pairs with one atomic.
+constexpr int kCompactPer = 8;
+constexpr int kCompactWaves = 256 / kWave;
 
-__global__ void __launch_bounds__(256) sv_hook(const int32_t* __restrict__ src,
-                                               const int32_t* __restrict__ dst, int64_t m_host,
-                                               const unsigned long long* m_dev,
-                                               int32_t* __restrict__ D,
-                                               const int32_t* __restrict__ NS,
-                                               int32_t* __restrict__ Q, int n,
-                                               int32_t* __restrict__ osrc,
-                                               int32_t* __restrict__ odst,
-                                               int2* __restrict__ ocache,
-                                               unsigned long long* m_out, int32_t* w, int s,
-                                               CcCtl* ctl) {
+__global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ src,
+                                                  const int32_t* __restrict__ dst, int64_t m_host,
+                                                  const unsigned long long* m_dev,
+                                                  const int32_t* __restrict__ D, int n,
+                                                  int32_t* __restrict__ osrc,
+                                                  int32_t* __restrict__ odst,
+                                                  int2* __restrict__ ocache,
+                                                  unsigned long long* m_out, const int32_t* w,
+                                                  int s, CcCtl* ctl) {
   if (converged(w, s)) return;
   const int64_t m = m_dev ? (int64_t)*m_dev : m_host;
-  __shared__ int cnt[kHookPer][kHookWaves];
+  __shared__ int cnt[kCompactPer][kCompactWaves];
   __shared__ unsigned long long chunk_base;
   const int wave = threadIdx.x / kWave;
-  const int64_t chunk = 256 * kHookPer;
-  bool hooked = false, bad = false;
+  const int64_t chunk = 256 * kCompactPer;
+  bool bad = false;
   for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < m; c0 += (int64_t)gridDim.x * chunk) {
-    int uu[kHookPer], vv[kHookPer], du[kHookPer], dv[kHookPer];
-    bool keep[kHookPer];
+    int uu[kCompactPer], vv[kCompactPer], du[kCompactPer], dv[kCompactPer];
+    bool keep[kCompactPer];
 #pragma unroll
-    for (int t = 0; t < kHookPer; ++t) {
+    for (int t = 0; t < kCompactPer; ++t) {
       const int64_t e = c0 + t * 256 + threadIdx.x;
       keep[t] = false;
       uu[t] = vv[t] = du[t] = dv[t] = 0;
@@ -141,34 +145,15 @@ __global__ void __launch_bounds__(256) sv_hook(const int32_t* __restrict__ src,
       }
     }
 #pragma unroll
-    for (int t = 0; t < kHookPer; ++t) {
-      if (!keep[t]) continue;
-      int a, b;
-      if (dv[t] < du[t]) {
-        a = du[t];
-        b = dv[t];
-      } else {
-        a = dv[t];
-        b = du[t];
-      }
-      if (D[a] == a && NS[a] != s) {
-        D[a] = b;
-        Q[a] = s;
-        Q[b] = s;
-        hooked = true;
-      }
-    }
-    // reserve output room for this chunk's survivors
-#pragma unroll
-    for (int t = 0; t < kHookPer; ++t) {
+    for (int t = 0; t < kCompactPer; ++t) {
       const uint64_t bm = __ballot(keep[t]);
       if (lane_id() == 0) cnt[t][wave] = __popcll(bm);
     }
     __syncthreads();
     if (threadIdx.x == 0) {
       int total = 0;
-      for (int t = 0; t < kHookPer; ++t)
-        for (int q = 0; q < kHookWaves; ++q) {
+      for (int t = 0; t < kCompactPer; ++t)
+        for (int q = 0; q < kCompactWaves; ++q) {
           const int c = cnt[t][q];
           cnt[t][q] = total;
           total += c;
@@ -178,7 +163,7 @@ __global__ void __launch_bounds__(256) sv_hook(const int32_t* __restrict__ src,
     __syncthreads();
     const unsigned long long cb = chunk_base;
 #pragma unroll
-    for (int t = 0; t < kHookPer; ++t) {
+    for (int t = 0; t < kCompactPer; ++t) {
       const uint64_t bm = __ballot(keep[t]);
       if (keep[t]) {
         const unsigned long long pos = cb + cnt[t][wave] + lanes_below(bm);
@@ -189,13 +174,37 @@ __global__ void __launch_bounds__(256) sv_hook(const int32_t* __restrict__ src,
     }
     __syncthreads();
   }
-  if (__ballot(hooked) && lane_id() == 0) w[s] = 1;
   if (__ballot(bad) && lane_id() == 0) atomicOr(&ctl->err, kErrRange);
 }
 
-// Step 3 over the survivors of step 2, reading the parents step 2 saw.  A
-// cached value is stale only for a root that step 2 hooked; such a tree is
-// not stagnant, and hooking onto a node of it still joins the right trees.
+// Step 2 over the surviving pairs, with the parents the compaction read at
+// the start of the step.
+__global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ cache,
+                                               const unsigned long long* m_dev,
+                                               int32_t* __restrict__ D,
+                                               const int32_t* __restrict__ NS,
+                                               int32_t* __restrict__ Q, int32_t* w, int s) {
+  if (converged(w, s)) return;
+  const int64_t m = (int64_t)*m_dev;
+  bool hooked = false;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int2 c = cache[e];
+    const int a = c.x > c.y ? c.x : c.y;
+    const int b = c.x > c.y ? c.y : c.x;
+    if (D[a] == a && NS[a] != s) {
+      D[a] = b;
+      Q[a] = s;
+      Q[b] = s;
+      hooked = true;
+    }
+  }
+  if (__ballot(hooked) && lane_id() == 0) w[s] = 1;
+}
+
+// Step 3 over the surviving pairs, with the parents read before step 2.  A
+// value is stale only for a root that step 2 hooked; such a tree is not
+// stagnant, and hooking onto a node of it still joins the right trees.
 __global__ void __launch_bounds__(256) sv_stagnant(const int2* __restrict__ cache,
                                                    const unsigned long long* m_dev,
                                                    int32_t* __restrict__ D,
@@ -408,7 +417,7 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
   const int gcap = cus * 16;
   const int gv = grid_for(n, 256, gcap);
   const int ge = grid_for(m, 256, gcap);
-  const int gh = grid_for((m + kHookPer - 1) / kHookPer, 256, gcap);
+  const int gh = grid_for((m + kCompactPer - 1) / kCompactPer, 256, gcap);
   int32_t* D = label;
 
   const int32_t* es = src;
@@ -445,9 +454,10 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
         const int32_t* isrc = s == 1 ? es : b.es[(s - 1) & 1];
         const int32_t* idst = s == 1 ? ed : b.ed[(s - 1) & 1];
         const unsigned long long* mdev = s == 1 ? nullptr : b.mcount + (s - 1);
-        hipLaunchKernelGGL(sv_hook, dim3(gh), dim3(256), 0, stream, isrc, idst, m, mdev, D, b.NS,
-                           b.Q, ni, b.es[s & 1], b.ed[s & 1], b.cache, b.mcount + s, b.w, s,
-                           b.ctl);
+        hipLaunchKernelGGL(sv_compact, dim3(gh), dim3(256), 0, stream, isrc, idst, m, mdev, D, ni,
+                           b.es[s & 1], b.ed[s & 1], b.cache, b.mcount + s, b.w, s, b.ctl);
+        hipLaunchKernelGGL(sv_hook, dim3(ge), dim3(256), 0, stream, b.cache, b.mcount + s, D,
+                           b.NS, b.Q, b.w, s);
         hipLaunchKernelGGL(sv_stagnant, dim3(ge), dim3(256), 0, stream, b.cache, b.mcount + s, D,
                            b.NS, b.Q, b.w, s);
       }

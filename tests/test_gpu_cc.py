@@ -130,3 +130,39 @@ def test_batched_matches_oracle(pj):
     got2 = pj.connected_components_batched(dev(src), dev(dst), dev(voff), dev(eoff))
     torch.cuda.synchronize()
     assert np.array_equal(got2.cpu().numpy(), want)
+
+
+def _mid_graph(i):
+    """Graphs of the serving mix whose parent arrays fit in one XCD's L2;
+    solves of these shapes once returned wrong labels with status OK."""
+    rng = np.random.default_rng(W.SEED_BASE + 5)
+    for _ in range(24):
+        rng.uniform(10, 24)
+    out = None
+    for k in range(i + 1):
+        n = int(np.floor(2 ** rng.uniform(10, 22)))
+        m = int(round(n * rng.uniform(2, 16) / 2))
+        if k == i:
+            out = (*W.random_graph(n, m, W.SEED_BASE + 5 + 100 + k), n)
+    return out
+
+
+def test_repeated_solves_are_always_correct(pj):
+    src, dst, n = _mid_graph(5)          # 838956 vertices, 5151345 pairs
+    want = oracle.connected_components(src, dst, n)
+    d_src, d_dst = dev(src), dev(dst)
+    for rep in range(24):
+        got = pj.connected_components(d_src, d_dst, n)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want), rep
+    s8, d8, n8 = _mid_graph(8)           # 149341 vertices, two copies in one batch
+    w8 = oracle.connected_components(s8, d8, n8)
+    voff = np.array([0, n8, 2 * n8], np.int64)
+    eoff = np.array([0, len(s8), 2 * len(s8)], np.int64)
+    bs, bd = dev(np.concatenate([s8, s8])), dev(np.concatenate([d8, d8]))
+    dvo, deo = dev(voff), dev(eoff)
+    for rep in range(24):
+        got = pj.connected_components_batched(bs, bd, dvo, deo, h_vtx_off=voff, h_edge_off=eoff)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy()
+        assert np.array_equal(got[:n8], w8) and np.array_equal(got[n8:], w8), rep
