@@ -42,6 +42,24 @@ struct CcCtl {
   int32_t rounds;
 };
 
+// Memory access discipline.  Within one kernel, other workgroups may write a
+// word of D, NS or Q while it is read, and several may write the same word
+// (two hooks of one root, many stamps of one root).  Loads are plain: a load
+// may return a value from the start of the kernel or any later one, and every
+// step below is correct under that (a stale D[a] == a only repeats a hook that
+// arbitrary concurrent writes allow; a stale parent is still an ancestor).
+// Stores of hooks and stamps are device-scope relaxed atomic stores, written
+// through to the device-coherent level.  With plain stores, such writes from
+// workgroups on different XCDs (each XCD has its own write-back L2) were seen
+// to be lost now and then: a lost stamp lets a root that received a hook look
+// stagnant and hook back (a cycle), and a lost hook makes a root a root again
+// after the pairs that joined it were dropped, splitting a component.  The
+// shortcut's store stays plain: each word has one writer, and losing it would
+// only leave an older ancestor in place.
+__device__ __forceinline__ void publish(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // The round-s kernels do nothing once an earlier round saw no change.
 __device__ __forceinline__ bool converged(const int32_t* w, int s) { return s > 1 && w[s - 1] == 0; }
 
@@ -88,7 +106,7 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
     const int p = D[v];
     const int gp = D[p];
     if (p != gp) {
-      NS[gp] = s;
+      if (NS[gp] != s) publish(&NS[gp], s);  // most marks repeat one root's stamp
       changed = true;
     }
   }
@@ -193,9 +211,9 @@ __global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ cache,
     const int a = c.x > c.y ? c.x : c.y;
     const int b = c.x > c.y ? c.y : c.x;
     if (D[a] == a && NS[a] != s) {
-      D[a] = b;
-      Q[a] = s;
-      Q[b] = s;
+      publish(&D[a], b);
+      publish(&Q[a], s);
+      if (Q[b] != s) publish(&Q[b], s);
       hooked = true;
     }
   }
@@ -219,10 +237,10 @@ __global__ void __launch_bounds__(256) sv_stagnant(const int2* __restrict__ cach
     const int2 c = cache[e];
     const int du = c.x, dv = c.y;
     if (D[du] == du && NS[du] != s && Q[du] != s) {
-      D[du] = dv;
+      publish(&D[du], dv);
       hooked = true;
     } else if (D[dv] == dv && NS[dv] != s && Q[dv] != s) {
-      D[dv] = du;
+      publish(&D[dv], du);
       hooked = true;
     }
   }

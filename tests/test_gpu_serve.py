@@ -156,3 +156,22 @@ def test_arrivals_while_busy_overlap(serve):
         assert s["completed"] == len(reqs)
         assert s["ticks"] > 1
         assert s["inflight_peak"] >= 2
+
+
+def test_sparse_graph_many_times(serve):
+    """A sparse graph (mean degree 2.3: a giant component with short pendant
+    paths) solved 400 times in the loop, mixed with denser graphs.  Lost
+    hook or stamp writes across the XCDs' L2 caches once split a pendant path
+    off its component in several percent of these solves."""
+    sparse = W.random_graph(127606, 148214, W.SEED_BASE + 108) + (127606,)
+    dense = [W.random_graph(n, m, 600 + n) + (n,) for n, m in ((32866, 212509), (7128, 48380))]
+    want = [oracle.connected_components(*g) for g in [sparse] + dense]
+    rng = np.random.default_rng(11)
+    picks = [0 if rng.random() < 0.8 else int(rng.integers(1, 3)) for _ in range(500)]
+    graphs = [sparse] + dense
+    with serve.Server(hbm_budget=2 << 30, max_inflight=2, max_batch=8) as srv:
+        ids = [srv.submit_cc(*graphs[j]) for j in picks]
+        for rid, j in zip(ids, picks):
+            st, _, out = srv.wait(rid, timeout_s=60)
+            assert st == 0
+            assert np.array_equal(out, want[j])
