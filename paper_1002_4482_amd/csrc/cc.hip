@@ -20,10 +20,9 @@
 //                         concurrent writes); the solve ends after the first
 //                         round with w[s] == 0.
 // Each pair is processed in both orientations by the thread that reads it.
-// Before step 2 a compaction kernel drops every pair whose two ends already
-// have the same parent (they lie in one tree, and trees only ever merge) and
-// writes the survivors, with their two parents, for steps 2 and 3 and for
-// the next round.
+// Before step 2 a compaction kernel replaces every pair by the pair of its
+// ends' parents and drops it when the two agree (see sv_compact); steps 2
+// and 3 read the survivors.  Round 1 starts from D = identity and skips 1a.
 // Concurrent writes to one root land in arbitrary order; every outcome is
 // one the arbitrary-CRCW algorithm allows: step 2 only hooks star roots onto
 // strictly smaller ids, step 3 only hooks stars that no step-2 hook touched,
@@ -113,51 +112,61 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
   if (__ballot(changed) && lane_id() == 0) w[s] = 1;
 }
 
-// Pair compaction, a kernel of its own between steps 1b and 2: keeps the
-// pairs whose ends have different parents (a pair whose ends share a parent
-// lies inside one tree for good, since trees only merge), together with the
-// two parents, which steps 2 and 3 of the round then read coalesced instead
-// of gathering.  D is not written while this kernel runs; that matters:
-// step 2 may hook one root twice (arbitrary winner), and a compaction decision
-// taken between those two writes could drop a pair that the second write
-// separates.  A workgroup reserves room for the survivors of each chunk of
+// Pair compaction, a kernel of its own between steps 1b and 2.  A stored
+// pair (x, y) stands for an input pair (i, j) with x in i's tree and y in j's
+// tree; it is replaced by (D[x], D[y]).  Parents lie in the same trees, so
+// the connectivity the pair carries is unchanged, and after round 1 the
+// stored ends are roots or near-roots: a shrinking set of words that stays
+// in cache, instead of gathers over the whole parent array every round.
+// Pairs whose two parents agree lie inside one tree for good (trees only
+// merge) and are dropped.  The survivors are exactly the parents steps 2 and
+// 3 need.  In round 1 every vertex is its own parent: the input pairs are
+// range-checked and copied without reading D.  D is not written while this
+// kernel runs: step 2 may hook one root twice (arbitrary winner), and a drop
+// decided between two such writes could rest on a parent the second write
+// replaces.  A workgroup reserves room for the survivors of each chunk of
 // kCompactPer * 256 pairs with one atomic.
 constexpr int kCompactPer = 8;
 constexpr int kCompactWaves = 256 / kWave;
 
+template <bool kFirst>
 __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ src,
-                                                  const int32_t* __restrict__ dst, int64_t m_host,
+                                                  const int32_t* __restrict__ dst,
+                                                  const int2* __restrict__ pin, int64_t m_host,
                                                   const unsigned long long* m_dev,
                                                   const int32_t* __restrict__ D, int n,
-                                                  int32_t* __restrict__ osrc,
-                                                  int32_t* __restrict__ odst,
-                                                  int2* __restrict__ ocache,
+                                                  int2* __restrict__ pout,
                                                   unsigned long long* m_out, const int32_t* w,
                                                   int s, CcCtl* ctl) {
   if (converged(w, s)) return;
-  const int64_t m = m_dev ? (int64_t)*m_dev : m_host;
+  const int64_t m = kFirst ? m_host : (int64_t)*m_dev;
   __shared__ int cnt[kCompactPer][kCompactWaves];
   __shared__ unsigned long long chunk_base;
   const int wave = threadIdx.x / kWave;
   const int64_t chunk = 256 * kCompactPer;
   bool bad = false;
   for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < m; c0 += (int64_t)gridDim.x * chunk) {
-    int uu[kCompactPer], vv[kCompactPer], du[kCompactPer], dv[kCompactPer];
+    int du[kCompactPer], dv[kCompactPer];
     bool keep[kCompactPer];
 #pragma unroll
     for (int t = 0; t < kCompactPer; ++t) {
       const int64_t e = c0 + t * 256 + threadIdx.x;
       keep[t] = false;
-      uu[t] = vv[t] = du[t] = dv[t] = 0;
+      du[t] = dv[t] = 0;
       if (e < m) {
-        const int u = src[e], v = dst[e];
-        if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) {
-          bad = true;
+        if (kFirst) {
+          const int u = src[e], v = dst[e];
+          if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) {
+            bad = true;
+          } else {
+            du[t] = u;
+            dv[t] = v;
+            keep[t] = u != v;
+          }
         } else {
-          uu[t] = u;
-          vv[t] = v;
-          du[t] = D[u];
-          dv[t] = D[v];
+          const int2 p = pin[e];
+          du[t] = D[p.x];
+          dv[t] = D[p.y];
           keep[t] = du[t] != dv[t];
         }
       }
@@ -183,21 +192,16 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
 #pragma unroll
     for (int t = 0; t < kCompactPer; ++t) {
       const uint64_t bm = __ballot(keep[t]);
-      if (keep[t]) {
-        const unsigned long long pos = cb + cnt[t][wave] + lanes_below(bm);
-        osrc[pos] = uu[t];
-        odst[pos] = vv[t];
-        ocache[pos] = make_int2(du[t], dv[t]);
-      }
+      if (keep[t]) pout[cb + cnt[t][wave] + lanes_below(bm)] = make_int2(du[t], dv[t]);
     }
     __syncthreads();
   }
-  if (__ballot(bad) && lane_id() == 0) atomicOr(&ctl->err, kErrRange);
+  if (kFirst && __ballot(bad) && lane_id() == 0) atomicOr(&ctl->err, kErrRange);
 }
 
-// Step 2 over the surviving pairs, with the parents the compaction read at
-// the start of the step.
-__global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ cache,
+// Step 2 over the surviving pairs: the parents the compaction read at the
+// start of the step.
+__global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ pairs,
                                                const unsigned long long* m_dev,
                                                int32_t* __restrict__ D,
                                                const int32_t* __restrict__ NS,
@@ -207,7 +211,7 @@ __global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ cache,
   bool hooked = false;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int2 c = cache[e];
+    const int2 c = pairs[e];
     const int a = c.x > c.y ? c.x : c.y;
     const int b = c.x > c.y ? c.y : c.x;
     if (D[a] == a && NS[a] != s) {
@@ -223,7 +227,7 @@ __global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ cache,
 // Step 3 over the surviving pairs, with the parents read before step 2.  A
 // value is stale only for a root that step 2 hooked; such a tree is not
 // stagnant, and hooking onto a node of it still joins the right trees.
-__global__ void __launch_bounds__(256) sv_stagnant(const int2* __restrict__ cache,
+__global__ void __launch_bounds__(256) sv_stagnant(const int2* __restrict__ pairs,
                                                    const unsigned long long* m_dev,
                                                    int32_t* __restrict__ D,
                                                    const int32_t* __restrict__ NS,
@@ -234,7 +238,7 @@ __global__ void __launch_bounds__(256) sv_stagnant(const int2* __restrict__ cach
   bool hooked = false;
   for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
        e += (int64_t)gridDim.x * blockDim.x) {
-    const int2 c = cache[e];
+    const int2 c = pairs[e];
     const int du = c.x, dv = c.y;
     if (D[du] == du && NS[du] != s && Q[du] != s) {
       publish(&D[du], dv);
@@ -367,9 +371,7 @@ struct CcBuffers {
   int32_t* gsrc = nullptr;
   int32_t* gdst = nullptr;
   int32_t* gerr = nullptr;               // batched: per-graph out-of-range flag
-  int32_t* es[2] = {};                   // compacted pair lists (ping-pong)
-  int32_t* ed[2] = {};
-  int2* cache = nullptr;                 // (D[i], D[j]) seen by step 2
+  int2* pairs[2] = {};                   // surviving parent pairs (ping-pong)
   int32_t* status_tmp = nullptr;
 };
 
@@ -387,11 +389,8 @@ size_t cc_carve(int64_t n, int64_t m, int64_t G, bool batched, bool want_status,
   take(b->w, (size_t)wlen);
   take(b->mcount, (size_t)wlen);
   const size_t mm = (size_t)std::max<int64_t>(m, 1);
-  take(b->es[0], mm);
-  take(b->ed[0], mm);
-  take(b->es[1], mm);
-  take(b->ed[1], mm);
-  take(b->cache, mm);
+  take(b->pairs[0], mm);
+  take(b->pairs[1], mm);
   if (batched) {
     take(b->gsrc, (size_t)std::max<int64_t>(m, 1));
     take(b->gdst, (size_t)std::max<int64_t>(m, 1));
@@ -465,19 +464,25 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
     const int chunk = std::min(o.rounds_per_check, max_rounds - rounds);
     for (int c = 0; c < chunk; ++c) {
       const int s = ++rounds;
-      hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
+      // D is the identity in round 1: no shortcut, and mark only records the round
+      if (s > 1) hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
       hipLaunchKernelGGL(sv_mark, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, b.w, s, b.ctl);
       if (m > 0) {
         // round 1 reads the input pairs, later rounds the survivors of the last one
-        const int32_t* isrc = s == 1 ? es : b.es[(s - 1) & 1];
-        const int32_t* idst = s == 1 ? ed : b.ed[(s - 1) & 1];
-        const unsigned long long* mdev = s == 1 ? nullptr : b.mcount + (s - 1);
-        hipLaunchKernelGGL(sv_compact, dim3(gh), dim3(256), 0, stream, isrc, idst, m, mdev, D, ni,
-                           b.es[s & 1], b.ed[s & 1], b.cache, b.mcount + s, b.w, s, b.ctl);
-        hipLaunchKernelGGL(sv_hook, dim3(ge), dim3(256), 0, stream, b.cache, b.mcount + s, D,
-                           b.NS, b.Q, b.w, s);
-        hipLaunchKernelGGL(sv_stagnant, dim3(ge), dim3(256), 0, stream, b.cache, b.mcount + s, D,
-                           b.NS, b.Q, b.w, s);
+        int2* out = b.pairs[s & 1];
+        if (s == 1)
+          hipLaunchKernelGGL(sv_compact<true>, dim3(gh), dim3(256), 0, stream, es, ed,
+                             (const int2*)nullptr, m, (const unsigned long long*)nullptr, D, ni,
+                             out, b.mcount + s, b.w, s, b.ctl);
+        else
+          hipLaunchKernelGGL(sv_compact<false>, dim3(gh), dim3(256), 0, stream,
+                             (const int32_t*)nullptr, (const int32_t*)nullptr,
+                             (const int2*)b.pairs[(s - 1) & 1], m, b.mcount + (s - 1), D, ni,
+                             out, b.mcount + s, b.w, s, b.ctl);
+        hipLaunchKernelGGL(sv_hook, dim3(ge), dim3(256), 0, stream, (const int2*)out,
+                           b.mcount + s, D, b.NS, b.Q, b.w, s);
+        hipLaunchKernelGGL(sv_stagnant, dim3(ge), dim3(256), 0, stream, (const int2*)out,
+                           b.mcount + s, D, b.NS, b.Q, b.w, s);
       }
       hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
     }
