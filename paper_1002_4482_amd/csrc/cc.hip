@@ -14,7 +14,8 @@
 //   2   conditional hook  edge (i,j), a = D[i]: if a is the root of a star and
 //                         b = D[j] < a: D[a] = b, Q[a] = Q[b] = s
 //   3   stagnant hook     if a is the root of a star with Q[a] != s and
-//                         b = D[j] != a: D[a] = b
+//                         b = D[j] != a: D[a] = b (the stagnant roots are
+//                         found first by a vertex pass, as a bitmap)
 //   4   shortcut          D[v] <- D[D[v]]
 //   5   change flag       any non-star mark or hook sets w[s] (an OR by
 //                         concurrent writes); the solve ends after the first
@@ -59,11 +60,45 @@ __device__ __forceinline__ void publish(int32_t* p, int32_t v) {
   __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// Device-scope relaxed load: sees what `publish` wrote from any XCD.
+__device__ __forceinline__ int32_t load_coherent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Raises a per-round flag (change or stagnant-root flag) from a workgroup-
+// wide OR.  Thousands of waves raise the same word in one kernel; a
+// write-through store per wave would serialise on that word, so a workgroup
+// stores at most once, and not at all once a coherent load shows it set.
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void raise_flag(int32_t* flag, bool mine) {
+  if (__syncthreads_or(mine) && threadIdx.x == 0 &&
+      __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    publish(flag, 1);
+}
+
 // The round-s kernels do nothing once an earlier round saw no change.
 __device__ __forceinline__ bool converged(const int32_t* w, int s) { return s > 1 && w[s - 1] == 0; }
 
+// Per-workgroup claim table in LDS (kClaim slots, cleared to -1 at kernel
+// start): true the first time `key` is offered in this workgroup, and when
+// its slot already holds another key.  Late in a solve thousands of pairs
+// hook or stamp the same few roots; the claim cuts their write-through stores
+// to about one per workgroup.  Which of several equal hooks lands is
+// arbitrary anyway.
+constexpr int kClaim = 1024;
+
+__device__ __forceinline__ void claim_clear(int* tab) {
+  for (int i = threadIdx.x; i < kClaim; i += blockDim.x) tab[i] = -1;
+  __syncthreads();
+}
+
+__device__ __forceinline__ bool claim(int* tab, int key) {
+  return atomicCAS(&tab[mix32((uint32_t)key) & (kClaim - 1)], -1, key) != key;
+}
+
 __global__ void sv_init(int32_t* __restrict__ D, int32_t* __restrict__ NS, int32_t* __restrict__ Q,
-                        int n, int32_t* w, unsigned long long* mcount, int wlen, CcCtl* ctl) {
+                        int n, int32_t* w, unsigned long long* mcount, int32_t* any, int wlen,
+                        CcCtl* ctl) {
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   for (int v = tid; v < n; v += stride) {
@@ -74,6 +109,7 @@ __global__ void sv_init(int32_t* __restrict__ D, int32_t* __restrict__ NS, int32
   for (int i = tid; i < wlen; i += stride) {
     w[i] = 0;
     mcount[i] = 0ull;
+    any[i] = 0;
   }
   if (tid == 0) {
     ctl->err = 0;
@@ -98,6 +134,8 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
                                                int32_t* __restrict__ NS, int n, int32_t* w,
                                                int s, CcCtl* ctl) {
   if (converged(w, s)) return;
+  __shared__ int tab[kClaim];
+  claim_clear(tab);
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->rounds = s;
   const int stride = gridDim.x * blockDim.x;
   bool changed = false;
@@ -105,11 +143,12 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
     const int p = D[v];
     const int gp = D[p];
     if (p != gp) {
-      if (NS[gp] != s) publish(&NS[gp], s);  // most marks repeat one root's stamp
+      // most marks repeat the stamp of one root
+      if (NS[gp] != s && claim(tab, gp)) publish(&NS[gp], s);
       changed = true;
     }
   }
-  if (__ballot(changed) && lane_id() == 0) w[s] = 1;
+  raise_flag(&w[s], changed);
 }
 
 // Pair compaction, a kernel of its own between steps 1b and 2.  A stored
@@ -128,6 +167,14 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
 // kCompactPer * 256 pairs with one atomic.
 constexpr int kCompactPer = 8;
 constexpr int kCompactWaves = 256 / kWave;
+// After round 1 a workgroup also drops repeats within its chunk: contracted
+// pairs pile up on the few roots that remain late in a solve (thousands of
+// copies of one pair of roots), and a copy joins nothing the first does not.
+// Open addressing in LDS, pairs ordered (min, max); a pair that finds no free
+// slot within kDedupProbes is kept.
+constexpr int kDedupSlots = 4096;  // >= 2 * 256 * kCompactPer
+constexpr int kDedupProbes = 8;
+constexpr unsigned long long kDedupEmpty = ~0ull;
 
 template <bool kFirst>
 __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ src,
@@ -142,10 +189,15 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
   const int64_t m = kFirst ? m_host : (int64_t)*m_dev;
   __shared__ int cnt[kCompactPer][kCompactWaves];
   __shared__ unsigned long long chunk_base;
+  __shared__ unsigned long long seen[kFirst ? 1 : kDedupSlots];
   const int wave = threadIdx.x / kWave;
   const int64_t chunk = 256 * kCompactPer;
   bool bad = false;
   for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < m; c0 += (int64_t)gridDim.x * chunk) {
+    if (!kFirst) {
+      for (int i = threadIdx.x; i < kDedupSlots; i += 256) seen[i] = kDedupEmpty;
+      __syncthreads();
+    }
     int du[kCompactPer], dv[kCompactPer];
     bool keep[kCompactPer];
 #pragma unroll
@@ -165,9 +217,26 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
           }
         } else {
           const int2 p = pin[e];
-          du[t] = D[p.x];
-          dv[t] = D[p.y];
-          keep[t] = du[t] != dv[t];
+          const int x = D[p.x], y = D[p.y];
+          du[t] = x < y ? x : y;
+          dv[t] = x < y ? y : x;
+          keep[t] = x != y;
+        }
+      }
+    }
+    if (!kFirst) {
+#pragma unroll
+      for (int t = 0; t < kCompactPer; ++t) {
+        if (!keep[t]) continue;
+        const unsigned long long key = ((unsigned long long)(unsigned)du[t] << 32) | (unsigned)dv[t];
+        unsigned h = mix32((unsigned)du[t] * 0x9E3779B1u ^ (unsigned)dv[t]);
+        for (int q = 0; q < kDedupProbes; ++q, ++h) {
+          const unsigned long long old = atomicCAS(&seen[h & (kDedupSlots - 1)], kDedupEmpty, key);
+          if (old == kDedupEmpty) break;             // first copy in this chunk
+          if (old == key) {                          // a repeat
+            keep[t] = false;
+            break;
+          }
         }
       }
     }
@@ -199,56 +268,125 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
   if (kFirst && __ballot(bad) && lane_id() == 0) atomicOr(&ctl->err, kErrRange);
 }
 
+// Pair kernels take kPairsPer pairs per thread per iteration, issuing all
+// their loads before using any, so that enough gathers are in flight.
+constexpr int kPairsPer = 8;
+
 // Step 2 over the surviving pairs: the parents the compaction read at the
-// start of the step.
+// start of the step.  In round 1 no tree is a non-star, so NS is not read.
+template <bool kFirst>
 __global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ pairs,
                                                const unsigned long long* m_dev,
                                                int32_t* __restrict__ D,
                                                const int32_t* __restrict__ NS,
                                                int32_t* __restrict__ Q, int32_t* w, int s) {
   if (converged(w, s)) return;
+  __shared__ int hooked_a[kClaim];  // roots this workgroup has hooked
+  __shared__ int stamped_b[kClaim];  // hook targets it has stamped
+  claim_clear(hooked_a);
+  claim_clear(stamped_b);
   const int64_t m = (int64_t)*m_dev;
+  const int64_t chunk = 256 * kPairsPer;
   bool hooked = false;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int2 c = pairs[e];
-    const int a = c.x > c.y ? c.x : c.y;
-    const int b = c.x > c.y ? c.y : c.x;
-    if (D[a] == a && NS[a] != s) {
-      publish(&D[a], b);
-      publish(&Q[a], s);
-      if (Q[b] != s) publish(&Q[b], s);
-      hooked = true;
+  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < m; c0 += (int64_t)gridDim.x * chunk) {
+    int a[kPairsPer], b[kPairsPer], da[kPairsPer];
+#pragma unroll
+    for (int t = 0; t < kPairsPer; ++t) {
+      const int64_t e = c0 + t * 256 + threadIdx.x;
+      const int2 c = e < m ? pairs[e] : make_int2(-1, -1);
+      a[t] = c.x > c.y ? c.x : c.y;
+      b[t] = c.x > c.y ? c.y : c.x;
+    }
+#pragma unroll
+    for (int t = 0; t < kPairsPer; ++t) da[t] = a[t] >= 0 ? D[a[t]] : -1;
+#pragma unroll
+    for (int t = 0; t < kPairsPer; ++t) {
+      // A thread that loses the claim acts as if it had seen a hooked already;
+      // the winner re-reads D[a] at the coherent level first, since late in a
+      // solve thousands of workgroups hook the same few roots.
+      if (a[t] >= 0 && da[t] == a[t] && (kFirst || NS[a[t]] != s) && claim(hooked_a, a[t]) &&
+          load_coherent(&D[a[t]]) == a[t]) {
+        publish(&D[a[t]], b[t]);
+        publish(&Q[a[t]], s);
+        if (Q[b[t]] != s && claim(stamped_b, b[t]) && load_coherent(&Q[b[t]]) != s)
+          publish(&Q[b[t]], s);
+        hooked = true;
+      }
     }
   }
-  if (__ballot(hooked) && lane_id() == 0) w[s] = 1;
+  raise_flag(&w[s], hooked);
 }
 
-// Step 3 over the surviving pairs, with the parents read before step 2.  A
-// value is stale only for a root that step 2 hooked; such a tree is not
-// stagnant, and hooking onto a node of it still joins the right trees.
+// Step 3, first pass: the stagnant roots (roots of stars that no step-2
+// hook touched: D[r] == r, NS[r] != s, Q[r] != s) as a bitmap, one ballot per
+// wave of 64 consecutive vertices; any[s] records whether there is one.  The
+// pair pass then tests bits of a small array (n / 8 bytes, cache-resident)
+// instead of gathering D, NS and Q for both ends of every pair.
+__global__ void __launch_bounds__(256) sv_stagnant_roots(const int32_t* __restrict__ D,
+                                                         const int32_t* __restrict__ NS,
+                                                         const int32_t* __restrict__ Q, int n,
+                                                         uint64_t* __restrict__ bits,
+                                                         int32_t* any, const int32_t* w, int s) {
+  if (converged(w, s)) return;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  bool found = false;
+  // the block size is a multiple of 64, so each wave covers one bitmap word
+  for (int64_t base = (int64_t)blockIdx.x * blockDim.x + threadIdx.x - lane_id(); base < n;
+       base += stride) {
+    const int64_t v = base + lane_id();
+    bool st = false;
+    if (v < n) st = D[v] == (int)v && NS[v] != s && Q[v] != s;
+    const uint64_t word = __ballot(st);
+    if (lane_id() == 0) bits[base >> 6] = word;
+    found |= word != 0;
+  }
+  raise_flag(&any[s], found);
+}
+
+__device__ __forceinline__ bool bit_set(const uint64_t* bits, int v) {
+  return (bits[v >> 6] >> (v & 63)) & 1ull;
+}
+
+// Step 3, pair pass, with the parents read before step 2: a stagnant root
+// hooks onto the other end's parent.  Two stagnant stars are never adjacent
+// (step 2 would have hooked one onto the other), so no cycle forms; a parent
+// that step 2 has since hooked is still a node of the tree it joins.
 __global__ void __launch_bounds__(256) sv_stagnant(const int2* __restrict__ pairs,
                                                    const unsigned long long* m_dev,
                                                    int32_t* __restrict__ D,
-                                                   const int32_t* __restrict__ NS,
-                                                   const int32_t* __restrict__ Q, int32_t* w,
-                                                   int s) {
-  if (converged(w, s)) return;
+                                                   const uint64_t* __restrict__ bits,
+                                                   const int32_t* any, int32_t* w, int s) {
+  if (converged(w, s) || any[s] == 0) return;
+  __shared__ int hooked_r[kClaim];
+  claim_clear(hooked_r);
   const int64_t m = (int64_t)*m_dev;
+  const int64_t chunk = 256 * kPairsPer;
   bool hooked = false;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int2 c = pairs[e];
-    const int du = c.x, dv = c.y;
-    if (D[du] == du && NS[du] != s && Q[du] != s) {
-      publish(&D[du], dv);
-      hooked = true;
-    } else if (D[dv] == dv && NS[dv] != s && Q[dv] != s) {
-      publish(&D[dv], du);
-      hooked = true;
+  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < m; c0 += (int64_t)gridDim.x * chunk) {
+    int2 c[kPairsPer];
+    bool bx[kPairsPer], by[kPairsPer];
+#pragma unroll
+    for (int t = 0; t < kPairsPer; ++t) {
+      const int64_t e = c0 + t * 256 + threadIdx.x;
+      c[t] = e < m ? pairs[e] : make_int2(-1, -1);
+    }
+#pragma unroll
+    for (int t = 0; t < kPairsPer; ++t) {
+      bx[t] = c[t].x >= 0 && bit_set(bits, c[t].x);
+      by[t] = c[t].y >= 0 && bit_set(bits, c[t].y);
+    }
+#pragma unroll
+    for (int t = 0; t < kPairsPer; ++t) {
+      if (bx[t]) {
+        if (claim(hooked_r, c[t].x)) publish(&D[c[t].x], c[t].y);
+        hooked = true;
+      } else if (by[t]) {
+        if (claim(hooked_r, c[t].y)) publish(&D[c[t].y], c[t].x);
+        hooked = true;
+      }
     }
   }
-  if (__ballot(hooked) && lane_id() == 0) w[s] = 1;
+  raise_flag(&w[s], hooked);
 }
 
 // ------------------------------------------------------- canonicalisation
@@ -367,7 +505,9 @@ struct CcBuffers {
   int32_t* NS = nullptr;
   int32_t* Q = nullptr;
   int32_t* w = nullptr;
-  unsigned long long* mcount = nullptr;  // surviving pairs after step 2 of each round
+  unsigned long long* mcount = nullptr;  // surviving pairs after compaction, per round
+  int32_t* stag_any = nullptr;           // a stagnant root exists, per round
+  uint64_t* stag_bits = nullptr;         // stagnant roots of the current round
   int32_t* gsrc = nullptr;
   int32_t* gdst = nullptr;
   int32_t* gerr = nullptr;               // batched: per-graph out-of-range flag
@@ -388,6 +528,8 @@ size_t cc_carve(int64_t n, int64_t m, int64_t G, bool batched, bool want_status,
   take(b->Q, (size_t)std::max<int64_t>(n, 1));
   take(b->w, (size_t)wlen);
   take(b->mcount, (size_t)wlen);
+  take(b->stag_any, (size_t)wlen);
+  take(b->stag_bits, (size_t)std::max<int64_t>((n + 63) / 64, 1));
   const size_t mm = (size_t)std::max<int64_t>(m, 1);
   take(b->pairs[0], mm);
   take(b->pairs[1], mm);
@@ -433,7 +575,7 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
   const int cus = device_info().cus;
   const int gcap = cus * 16;
   const int gv = grid_for(n, 256, gcap);
-  const int ge = grid_for(m, 256, gcap);
+  const int gp = grid_for((m + kPairsPer - 1) / kPairsPer, 256, gcap);
   const int gh = grid_for((m + kCompactPer - 1) / kCompactPer, 256, gcap);
   int32_t* D = label;
 
@@ -450,7 +592,7 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
     }
   }
   hipLaunchKernelGGL(sv_init, dim3(gv), dim3(256), 0, stream, D, b.NS, b.Q, ni, b.w, b.mcount,
-                     wlen, b.ctl);
+                     b.stag_any, wlen, b.ctl);
   PJ_HIP(hipGetLastError());
   tm.mark("sv0_init");
 
@@ -479,10 +621,18 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
                              (const int32_t*)nullptr, (const int32_t*)nullptr,
                              (const int2*)b.pairs[(s - 1) & 1], m, b.mcount + (s - 1), D, ni,
                              out, b.mcount + s, b.w, s, b.ctl);
-        hipLaunchKernelGGL(sv_hook, dim3(ge), dim3(256), 0, stream, (const int2*)out,
-                           b.mcount + s, D, b.NS, b.Q, b.w, s);
-        hipLaunchKernelGGL(sv_stagnant, dim3(ge), dim3(256), 0, stream, (const int2*)out,
-                           b.mcount + s, D, b.NS, b.Q, b.w, s);
+        if (s == 1)
+          hipLaunchKernelGGL(sv_hook<true>, dim3(gp), dim3(256), 0, stream, (const int2*)out,
+                             b.mcount + s, D, b.NS, b.Q, b.w, s);
+        else
+          hipLaunchKernelGGL(sv_hook<false>, dim3(gp), dim3(256), 0, stream, (const int2*)out,
+                             b.mcount + s, D, b.NS, b.Q, b.w, s);
+        hipLaunchKernelGGL(sv_stagnant_roots, dim3(gv), dim3(256), 0, stream, (const int32_t*)D,
+                           (const int32_t*)b.NS, (const int32_t*)b.Q, ni, b.stag_bits,
+                           b.stag_any, b.w, s);
+        hipLaunchKernelGGL(sv_stagnant, dim3(gp), dim3(256), 0, stream, (const int2*)out,
+                           b.mcount + s, D, (const uint64_t*)b.stag_bits,
+                           (const int32_t*)b.stag_any, b.w, s);
       }
       hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
     }
