@@ -73,7 +73,8 @@ typedef struct pj_opts {
     int32_t algo;             /* PJ_ALGO_* */
     int32_t block;            /* threads per workgroup, multiple of 64 in [64, 1024] */
     int32_t spacing;          /* ruling set, first level: one splitter per `spacing`
-                                 consecutive node ids (power of two, 2..65536) */
+                                 consecutive node ids (power of two, 2..65536);
+                                 zero: 16, 32 or 64 as n grows past 2^24, 2^25 */
     int32_t spacing_up;       /* ruling set, recursion levels: same meaning */
     int32_t cutoff;           /* ruling set: a level with at most this many nodes is ranked
                                  by one workgroup in LDS (64..16384) */

@@ -12,7 +12,8 @@
 //   1b  mark non-stars    if D[v] != D[D[v]]: NS[D[D[v]]] = s
 //       (1a must be complete for every vertex first, hence two kernels)
 //   2   conditional hook  edge (i,j), a = D[i]: if a is the root of a star and
-//                         b = D[j] < a: D[a] = b, Q[a] = Q[b] = s
+//                         b = D[j] < a: D[a] = b, Q[b] = s (SV also
+//                         stamps a, but a hooked root is never tested again)
 //   3   stagnant hook     if a is the root of a star with Q[a] != s and
 //                         b = D[j] != a: D[a] = b (the stagnant roots are
 //                         found first by a vertex pass, as a bitmap)
@@ -306,8 +307,9 @@ __global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ pairs,
       // solve thousands of workgroups hook the same few roots.
       if (a[t] >= 0 && da[t] == a[t] && (kFirst || NS[a[t]] != s) && claim(hooked_a, a[t]) &&
           load_coherent(&D[a[t]]) == a[t]) {
+        // Q[a] is not stamped: a hooked root is no root any more, so it is
+        // never tested for stagnation
         publish(&D[a[t]], b[t]);
-        publish(&Q[a[t]], s);
         if (Q[b[t]] != s && claim(stamped_b, b[t]) && load_coherent(&Q[b[t]]) != s)
           publish(&Q[b[t]], s);
         hooked = true;

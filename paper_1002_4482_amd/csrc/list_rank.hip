@@ -816,6 +816,16 @@ __global__ void lr_status(const LrCtl* ctl, const int32_t* lerr, const int32_t* 
 }
 
 // ------------------------------------------------------------------ host
+// First-level splitter spacing when the caller leaves it at zero: about 2^20
+// splitters, so the splitter ranks that the final scatter gathers (4 B each)
+// stay near one XCD's 4 MiB L2, between 16 (short walks for small,
+// latency-bound lists) and 64 (longer walks only add imbalance).
+inline int default_spacing(int64_t n) {
+  int sp = 16;
+  while (sp < 64 && (n >> 20) > sp) sp *= 2;
+  return sp;
+}
+
 inline int ilog2(int v) {
   int r = 0;
   while ((1 << r) < v) ++r;
@@ -1003,7 +1013,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     pj_opts_init(&raw);
     if (user) raw = *user;
     apply_tuned(raw, n0, L);
-    o.spacing = raw.spacing > 0 ? raw.spacing : o.spacing;
+    o.spacing = raw.spacing > 0 ? raw.spacing : default_spacing(n0);
     o.spacing_up = raw.spacing_up > 0 ? raw.spacing_up : o.spacing_up;
     o.cutoff = raw.cutoff > 0 ? std::min(std::max(raw.cutoff, 64), 16384) : o.cutoff;
     o.max_walk = raw.max_walk > 0 ? std::max(raw.max_walk, 16) : o.max_walk;
@@ -1227,6 +1237,7 @@ size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool sing
   pj_opts_init(&raw);
   if (user) raw = *user;
   apply_tuned(raw, n0, L);
+  if (raw.spacing <= 0) raw.spacing = default_spacing(n0);
   pj_opts o = resolved_opts(&raw);
   Plan p = make_plan(n0, L, n0, o);
   Buffers b;
