@@ -59,18 +59,31 @@ def traffic_from_profile(name, src_files):
     return rec.get("hbm_bytes_per_launch")
 
 
-def timed(torch, fn, steps, warmup):
+def timed(torch, fn, steps, warmup, per_step=None):
+    """Mean ms per step over `steps` back-to-back calls on the current stream
+    (events between steps, one synchronisation at the end).  If `per_step`
+    is a list, the individual step times are appended to it."""
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    t0.record()
-    for _ in range(steps):
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    ev[0].record()
+    for i in range(steps):
         fn()
-    t1.record()
+        ev[i + 1].record()
     torch.cuda.synchronize()
-    return t0.elapsed_time(t1) / steps
+    if per_step is not None:
+        per_step.extend(ev[i].elapsed_time(ev[i + 1]) for i in range(steps))
+    return ev[0].elapsed_time(ev[steps]) / steps
+
+
+def copy_peak_gbs(torch, dev):
+    """Achievable HBM rate of a plain 256 MiB device copy (read + write bytes)."""
+    a = torch.empty(1 << 26, dtype=torch.int32, device=dev)
+    b = torch.empty_like(a)
+    ms = timed(torch, lambda: b.copy_(a), 10, 3)
+    del a, b
+    return 2 * (1 << 28) / (ms * 1e-3) / 1e9
 
 
 def phase_means(stats_list):
@@ -131,7 +144,8 @@ def main():
         pj.list_rank(d_succ, d_rank, algo="ruling_set")
 
     log(f"timing ruling set: warmup {args.warmup}, steps {args.steps}")
-    ms = timed(torch, step, args.steps, args.warmup)
+    step_ms = []
+    ms = timed(torch, step, args.steps, args.warmup, step_ms)
     # correctness of what was timed: closed form rank[order[k]] = k
     ok = bool(torch.equal(d_rank[torch.from_numpy(order).to(dev).long()],
                           torch.arange(n, dtype=torch.int32, device=dev)))
@@ -139,7 +153,10 @@ def main():
     if not ok:
         raise SystemExit("ranking mismatch on the timed workload")
 
-    # per-phase device times (HIP events recorded by the library on its stream)
+    # per-phase device times: HIP events the library records on its stream
+    # around each phase, over as many stats-enabled steps right after the
+    # timed ones (reading them back needs a synchronisation per step, which
+    # is kept out of the timed region)
     stats = []
     for _ in range(max(3, min(args.steps, 10))):
         _, st = pj.list_rank(d_succ, d_rank, algo="ruling_set", return_stats=True)
@@ -148,6 +165,7 @@ def main():
     walk_ms = phases.get("walk0", float("nan"))
     achieved = LR_BYTES_PER_NODE * n / (walk_ms * 1e-3) / 1e9
     traffic = traffic_from_profile("walk0_u26_traffic.json", ["list_rank.hip"])
+    copy_gbs = copy_peak_gbs(torch, dev)
     roofline = {
         "bound": "hbm",
         "achieved": round(achieved, 1),
@@ -158,11 +176,18 @@ def main():
         "kernel": "lr_walk level 0 (sublist walks)",
         "kernel_ms": round(walk_ms, 4),
         "bytes_per_node": LR_BYTES_PER_NODE,
+        "copy_peak": round(copy_gbs, 1),
+        "frac_of_copy": round(achieved / copy_gbs, 4),
+        "traffic_per_node": round(traffic / n, 1) if traffic else None,
+        "amplification": round(traffic / (LR_BYTES_PER_NODE * n), 1) if traffic else None,
+        "traffic_rate": round(traffic / (walk_ms * 1e-3) / 1e9, 1) if traffic else None,
     }
     path_gbs = LR_BYTES_PER_NODE * n / (ms * 1e-3) / 1e9
     log(f"phases {phases}")
 
     extras = {
+        "step_ms": {"mean": round(float(np.mean(step_ms)), 4), "sd": round(float(np.std(step_ms)), 4),
+                    "median": round(float(np.median(step_ms)), 4)},
         "phases_ms": {k: round(v, 4) for k, v in phases.items()},
         "levels": stats[-1]["levels"],
         "level_nodes": stats[-1]["level_nodes"],

@@ -303,14 +303,15 @@ __global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ pairs,
 #pragma unroll
     for (int t = 0; t < kPairsPer; ++t) {
       // A thread that loses the claim acts as if it had seen a hooked already;
-      // the winner re-reads D[a] at the coherent level first, since late in a
-      // solve thousands of workgroups hook the same few roots.
+      // after round 1 the winner re-reads D[a] at the coherent level first,
+      // since late in a solve thousands of workgroups hook the same few roots
+      // (in round 1 a root is the larger end of only ~m/n pairs).
       if (a[t] >= 0 && da[t] == a[t] && (kFirst || NS[a[t]] != s) && claim(hooked_a, a[t]) &&
-          load_coherent(&D[a[t]]) == a[t]) {
+          (kFirst || load_coherent(&D[a[t]]) == a[t])) {
         // Q[a] is not stamped: a hooked root is no root any more, so it is
         // never tested for stagnation
         publish(&D[a[t]], b[t]);
-        if (Q[b[t]] != s && claim(stamped_b, b[t]) && load_coherent(&Q[b[t]]) != s)
+        if (Q[b[t]] != s && claim(stamped_b, b[t]) && (kFirst || load_coherent(&Q[b[t]]) != s))
           publish(&Q[b[t]], s);
         hooked = true;
       }
