@@ -155,15 +155,18 @@ void pj_graph_cache_clear(void);
 
 /* ------------------------------------------------------------- autotuner */
 /*
- * Times ruling-set parameter sets (first-level spacing 4..64, recursion
- * spacing 4..16) on this input and records the fastest in the tune cache,
- * keyed by (gfx arch, ceil(log2 nodes), ceil(log2 lists)).  Later list-ranking
- * calls whose spacing / spacing_up / cutoff / max_walk are zero use the cached
- * values for their size class; results never depend on them.  offsets == NULL
- * tunes the single-list call on n nodes; otherwise offsets is the device
- * table and h_offsets its host copy (required).  Writes the chosen options to
- * *best and their mean time to *best_ms (either may be NULL).  Allocates a
- * scratch output, runs ~60 solves and synchronises the stream.
+ * Times ruling-set parameters on this input by coordinate descent from the
+ * defaults (first-level spacing 8..128, recursion spacing 4..16, LDS cutoff
+ * 2048..16384, workgroup size of the sublist walks 128..1024, each swept with
+ * the others at their best so far) and records the fastest in the tune
+ * cache, keyed by (gfx arch, ceil(log2 nodes), ceil(log2 lists)).  Later
+ * list-ranking calls whose spacing / spacing_up / cutoff / max_walk / block
+ * are zero use the cached values for their size class; results never depend
+ * on them.  offsets == NULL tunes the single-list call on n nodes; otherwise
+ * offsets is the device table and h_offsets its host copy (required).  Writes
+ * the chosen options to *best and their mean time to *best_ms (either may be
+ * NULL).  Allocates a scratch output, runs ~60 solves and synchronises the
+ * stream.
  */
 int pj_tune_list_rank(const int32_t *succ, const int64_t *offsets, int64_t L,
                       const int64_t *h_offsets, int64_t n, pj_opts *best, float *best_ms,

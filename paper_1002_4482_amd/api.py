@@ -167,7 +167,7 @@ def tune_list_rank(succ, offsets=None, *, h_offsets=None, stream=None):
                                    ctypes.byref(ms), _stream_ptr(stream))
     _check(rc, "pj_tune_list_rank")
     return ({"spacing": best.spacing, "spacing_up": best.spacing_up, "cutoff": best.cutoff,
-             "max_walk": best.max_walk}, float(ms.value))
+             "max_walk": best.max_walk, "block": best.block}, float(ms.value))
 
 
 def tune_lookup(n, L=1):
@@ -176,7 +176,7 @@ def tune_lookup(n, L=1):
     if rc != _lib.PJ_OK:
         return None
     return {"spacing": o.spacing, "spacing_up": o.spacing_up, "cutoff": o.cutoff,
-            "max_walk": o.max_walk}
+            "max_walk": o.max_walk, "block": o.block}
 
 
 def tune_save(path):

@@ -36,7 +36,7 @@ int bits_for(int64_t v) {
 
 // ------------------------------------------------------------ tune cache
 struct Tuned {
-  int spacing, spacing_up, cutoff, max_walk;
+  int spacing, spacing_up, cutoff, max_walk, block;
   float ms;
 };
 using TuneKey = std::tuple<std::string, int, int>;
@@ -44,6 +44,7 @@ using TuneKey = std::tuple<std::string, int, int>;
 std::mutex g_tune_mu;
 std::map<TuneKey, Tuned> g_tune;
 bool g_tune_env_loaded = false;
+int64_t g_tune_gen = 0;  // bumped on every change, part of the graph cache key
 
 int load_locked(const char* path) {
   FILE* f = fopen(path, "r");
@@ -51,9 +52,10 @@ int load_locked(const char* path) {
   char arch[128];
   int nb, lb;
   Tuned t;
-  while (fscanf(f, "%127s %d %d %d %d %d %d %f", arch, &nb, &lb, &t.spacing, &t.spacing_up,
-                &t.cutoff, &t.max_walk, &t.ms) == 8)
+  while (fscanf(f, "%127s %d %d %d %d %d %d %d %f", arch, &nb, &lb, &t.spacing, &t.spacing_up,
+                &t.cutoff, &t.max_walk, &t.block, &t.ms) == 9)
     g_tune[TuneKey(arch, nb, lb)] = t;
+  ++g_tune_gen;
   fclose(f);
   return PJ_OK;
 }
@@ -86,7 +88,7 @@ void drop_entry(GraphEntry& e) {
 }  // namespace
 
 void apply_tuned(pj_opts& o, int64_t n0, int64_t L) {
-  if (o.spacing > 0 && o.spacing_up > 0 && o.cutoff > 0 && o.max_walk > 0) return;
+  if (o.spacing > 0 && o.spacing_up > 0 && o.cutoff > 0 && o.max_walk > 0 && o.block > 0) return;
   std::lock_guard<std::mutex> lk(g_tune_mu);
   if (!g_tune_env_loaded) {
     g_tune_env_loaded = true;
@@ -100,6 +102,7 @@ void apply_tuned(pj_opts& o, int64_t n0, int64_t L) {
   if (o.spacing_up <= 0) o.spacing_up = t.spacing_up;
   if (o.cutoff <= 0) o.cutoff = t.cutoff;
   if (o.max_walk <= 0) o.max_walk = t.max_walk;
+  if (o.block <= 0) o.block = t.block;
 }
 
 int graph_batched(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,
@@ -125,6 +128,10 @@ int graph_batched(const int32_t* succ, const int64_t* d_off, int64_t L, const in
                user.block,
                0,
                0};
+  {
+    std::lock_guard<std::mutex> tl(g_tune_mu);
+    key[16] = g_tune_gen;  // zero parameters may resolve differently after a retune
+  }
   std::lock_guard<std::mutex> lk(g_graph_mu);
   auto it = g_graphs.find(key);
   if (it == g_graphs.end()) {
@@ -194,37 +201,52 @@ int pj_tune_list_rank(const int32_t* succ, const int64_t* offsets, int64_t L,
   hipEvent_t e0, e1;
   PJ_HIP(hipEventCreate(&e0));
   PJ_HIP(hipEventCreate(&e1));
-  const int spacings[] = {4, 8, 16, 32, 64};
-  const int ups[] = {4, 8, 16};
-  pj::Tuned bestt{16, 8, 16384, 1024, 1e30f};
+  // Coordinate descent from the library defaults: first-level spacing, then
+  // recursion spacing, LDS cutoff and workgroup size, each swept with the
+  // others held at their best so far (1 warm-up and 3 timed solves each).
+  pj::Tuned cur{0, 8, 16384, 1024, 256, 1e30f};
+  cur.spacing = pj::list_rank_default_spacing(n0);
+  const std::vector<int> sweeps[4] = {{8, 16, 32, 64, 128}, {4, 8, 16}, {2048, 4096, 8192, 16384},
+                                      {128, 256, 512, 1024}};
   int rc = PJ_OK;
-  for (int sp : spacings) {
-    for (int up : ups) {
-      pj_opts o;
-      pj_opts_init(&o);
-      o.algo = PJ_ALGO_RULING_SET;
-      o.spacing = sp;
-      o.spacing_up = up;
-      o.cutoff = 16384;
-      o.max_walk = 1024;
-      o.h_offsets = h_offsets;
-      auto run = [&] {
-        return single ? pj::list_rank_impl(succ, nullptr, 1, nullptr, n0, out, &o, s)
-                      : pj::list_rank_impl(succ, offsets, L, h_offsets, 0, out, &o, s);
-      };
-      rc = run();  // warm-up
+  auto time_one = [&](const pj::Tuned& t, float* ms_out) -> int {
+    pj_opts o;
+    pj_opts_init(&o);
+    o.algo = PJ_ALGO_RULING_SET;
+    o.spacing = t.spacing;
+    o.spacing_up = t.spacing_up;
+    o.cutoff = t.cutoff;
+    o.max_walk = t.max_walk;
+    o.block = t.block;
+    o.h_offsets = h_offsets;
+    auto run = [&] {
+      return single ? pj::list_rank_impl(succ, nullptr, 1, nullptr, n0, out, &o, s)
+                    : pj::list_rank_impl(succ, offsets, L, h_offsets, 0, out, &o, s);
+    };
+    int r = run();  // warm-up
+    if (r != PJ_OK) return r;
+    PJ_HIP(hipEventRecord(e0, s));
+    for (int k = 0; k < 3 && r == PJ_OK; ++k) r = run();
+    PJ_HIP(hipEventRecord(e1, s));
+    PJ_HIP(hipEventSynchronize(e1));
+    float ms = 0.f;
+    PJ_HIP(hipEventElapsedTime(&ms, e0, e1));
+    *ms_out = ms / 3.f;
+    return r;
+  };
+  rc = time_one(cur, &cur.ms);
+  for (int dim = 0; dim < 4 && rc == PJ_OK; ++dim) {
+    for (int v : sweeps[dim]) {
+      pj::Tuned t = cur;
+      int* field = dim == 0 ? &t.spacing : dim == 1 ? &t.spacing_up : dim == 2 ? &t.cutoff : &t.block;
+      if (*field == v) continue;
+      *field = v;
+      rc = time_one(t, &t.ms);
       if (rc != PJ_OK) break;
-      PJ_HIP(hipEventRecord(e0, s));
-      for (int r = 0; r < 3 && rc == PJ_OK; ++r) rc = run();
-      PJ_HIP(hipEventRecord(e1, s));
-      PJ_HIP(hipEventSynchronize(e1));
-      float ms = 0.f;
-      PJ_HIP(hipEventElapsedTime(&ms, e0, e1));
-      ms /= 3.f;
-      if (rc == PJ_OK && ms < bestt.ms) bestt = pj::Tuned{sp, up, 16384, 1024, ms};
+      if (t.ms < cur.ms) cur = t;
     }
-    if (rc != PJ_OK) break;
   }
+  const pj::Tuned bestt = cur;
   (void)hipFreeAsync(out, s);
   (void)hipStreamSynchronize(s);
   (void)hipEventDestroy(e0);
@@ -233,6 +255,7 @@ int pj_tune_list_rank(const int32_t* succ, const int64_t* offsets, int64_t L,
   {
     std::lock_guard<std::mutex> lk(pj::g_tune_mu);
     pj::g_tune[pj::tune_key(n0, L)] = bestt;
+    ++pj::g_tune_gen;
   }
   if (best) {
     pj_opts_init(best);
@@ -241,6 +264,7 @@ int pj_tune_list_rank(const int32_t* succ, const int64_t* offsets, int64_t L,
     best->spacing_up = bestt.spacing_up;
     best->cutoff = bestt.cutoff;
     best->max_walk = bestt.max_walk;
+    best->block = bestt.block;
   }
   if (best_ms) *best_ms = bestt.ms;
   return PJ_OK;
@@ -253,8 +277,9 @@ int pj_tune_save(const char* path) {
   if (!f) return PJ_EINVAL;
   for (auto& kv : pj::g_tune) {
     const auto& t = kv.second;
-    fprintf(f, "%s %d %d %d %d %d %d %.4f\n", std::get<0>(kv.first).c_str(), std::get<1>(kv.first),
-            std::get<2>(kv.first), t.spacing, t.spacing_up, t.cutoff, t.max_walk, t.ms);
+    fprintf(f, "%s %d %d %d %d %d %d %d %.4f\n", std::get<0>(kv.first).c_str(),
+            std::get<1>(kv.first), std::get<2>(kv.first), t.spacing, t.spacing_up, t.cutoff,
+            t.max_walk, t.block, t.ms);
   }
   fclose(f);
   return PJ_OK;
@@ -269,6 +294,7 @@ int pj_tune_load(const char* path) {
 void pj_tune_clear(void) {
   std::lock_guard<std::mutex> lk(pj::g_tune_mu);
   pj::g_tune.clear();
+  ++pj::g_tune_gen;
 }
 
 int pj_tune_lookup(int64_t n, int64_t L, pj_opts* out) {

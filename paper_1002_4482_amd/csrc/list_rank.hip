@@ -246,7 +246,7 @@ struct WalkArgs {
 // state.  The read and the write then touch the same cache line, which costs
 // far less than a write to a second random line.
 template <bool kLevel0, bool kBatched, bool kPacked>
-__global__ void __launch_bounds__(256) lr_walk(WalkArgs a) {
+__global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
   LrCtl* ctl = a.ctl;
   const int N = level_nodes(ctl, a.level, a.L, a.cap_prev);
   const int log2B = a.log2B;
@@ -816,16 +816,6 @@ __global__ void lr_status(const LrCtl* ctl, const int32_t* lerr, const int32_t* 
 }
 
 // ------------------------------------------------------------------ host
-// First-level splitter spacing when the caller leaves it at zero: about 2^20
-// splitters, so the splitter ranks that the final scatter gathers (4 B each)
-// stay near one XCD's 4 MiB L2, between 16 (short walks for small,
-// latency-bound lists) and 64 (longer walks only add imbalance).
-inline int default_spacing(int64_t n) {
-  int sp = 16;
-  while (sp < 64 && (n >> 20) > sp) sp *= 2;
-  return sp;
-}
-
 inline int ilog2(int v) {
   int r = 0;
   while ((1 << r) < v) ++r;
@@ -1013,10 +1003,11 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     pj_opts_init(&raw);
     if (user) raw = *user;
     apply_tuned(raw, n0, L);
-    o.spacing = raw.spacing > 0 ? raw.spacing : default_spacing(n0);
+    o.spacing = raw.spacing > 0 ? raw.spacing : list_rank_default_spacing(n0);
     o.spacing_up = raw.spacing_up > 0 ? raw.spacing_up : o.spacing_up;
     o.cutoff = raw.cutoff > 0 ? std::min(std::max(raw.cutoff, 64), 16384) : o.cutoff;
     o.max_walk = raw.max_walk > 0 ? std::max(raw.max_walk, 16) : o.max_walk;
+    if (raw.block > 0) o.block = std::min(1024, (raw.block + 63) / 64 * 64);
   }
   Plan p = make_plan(n0, L, max_size, o);
   Buffers b;
@@ -1129,10 +1120,12 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
       else if (single) kfn = p.packed ? lr_walk<true, false, true> : lr_walk<true, false, false>;
       else kfn = p.packed ? lr_walk<true, true, true> : lr_walk<true, true, false>;
       const int64_t items = ((p.bound[lv] + (1ll << a.log2B) - 1) >> a.log2B) + L;
-      int g = persistent_grid((const void*)kfn, 256, 0);
-      g = (int)std::min<int64_t>(g, (items + 255) / 256);
+      // workgroup size o.block (tunable): it sets how many lanes share one
+      // LDS work counter and contiguous range of splitters
+      int g = persistent_grid((const void*)kfn, blk, 0);
+      g = (int)std::min<int64_t>(g, (items + blk - 1) / blk);
       if (g < 1) g = 1;
-      hipLaunchKernelGGL(kfn, dim3(g), dim3(256), 0, stream, a);
+      hipLaunchKernelGGL(kfn, dim3(g), dim3(blk), 0, stream, a);
       PJ_HIP(hipGetLastError());
       tm.mark(lv == 0 ? "walk0" : "walk_up");
     }
@@ -1232,12 +1225,22 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
   return result;
 }
 
+// First-level splitter spacing when the caller leaves it at zero: about 2^20
+// splitters, so the splitter ranks that the final scatter gathers (4 B each)
+// stay near one XCD's 4 MiB L2, between 16 (short walks for small,
+// latency-bound lists) and 64 (longer walks only add imbalance).
+int list_rank_default_spacing(int64_t n) {
+  int sp = 16;
+  while (sp < 64 && (n >> 20) > sp) sp *= 2;
+  return sp;
+}
+
 size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single) {
   pj_opts raw;
   pj_opts_init(&raw);
   if (user) raw = *user;
   apply_tuned(raw, n0, L);
-  if (raw.spacing <= 0) raw.spacing = default_spacing(n0);
+  if (raw.spacing <= 0) raw.spacing = list_rank_default_spacing(n0);
   pj_opts o = resolved_opts(&raw);
   Plan p = make_plan(n0, L, n0, o);
   Buffers b;

@@ -73,7 +73,8 @@ def test_paper_tail_convention_and_to_tail(pj):
 @pytest.mark.parametrize("params", [
     dict(spacing=2), dict(spacing=4, spacing_up=2), dict(spacing=64, spacing_up=32),
     dict(spacing=1024), dict(max_walk=16), dict(cutoff=64), dict(seed=12345),
-    dict(block=64), dict(spacing=8, cutoff=256, max_walk=20, seed=7),
+    dict(block=64), dict(block=512), dict(block=1024, spacing=128),
+    dict(spacing=8, cutoff=256, max_walk=20, seed=7),
 ])
 def test_parameters_do_not_change_ranks(pj, params):
     n = 400_009
@@ -291,7 +292,9 @@ def test_autotune_picks_parameters_and_keeps_results(pj, tmp_path):
     d_succ = dev(succ)
     pj.tune_clear()
     best, ms = pj.tune_list_rank(d_succ)
-    assert best["spacing"] in (4, 8, 16, 32, 64) and ms > 0
+    assert best["spacing"] in (8, 16, 32, 64, 128) and best["spacing_up"] in (4, 8, 16)
+    assert best["cutoff"] in (2048, 4096, 8192, 16384) and best["block"] in (128, 256, 512, 1024)
+    assert ms > 0
     assert pj.tune_lookup(n) == best
     got = pj.list_rank(d_succ)   # uses the tuned parameters
     torch.cuda.synchronize()
