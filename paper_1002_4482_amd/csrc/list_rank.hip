@@ -49,7 +49,11 @@ struct LrCtl {
   int32_t err;
   int32_t pad;
   unsigned long long base_total;  // total weight seen by the base ranking
+  unsigned long long near;        // single list: successors within kNear ids
 };
+
+// A successor within kNear ids of its node counts as local (see lr_walk).
+constexpr int kNear = 64;
 
 // Node count of level `level` >= 1: static + virtual + granted cut points of
 // the level below.
@@ -104,9 +108,10 @@ template <bool kCopy>
 __global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restrict__ succ, int n,
                                                           int32_t* __restrict__ copy,
                                                           unsigned long long* lsum,
-                                                          int32_t* ltails, int32_t* lerr) {
+                                                          int32_t* ltails, int32_t* lerr,
+                                                          unsigned long long* lnear) {
   unsigned long long acc = 0;
-  int tails = 0, bad = 0;
+  int tails = 0, bad = 0, near = 0;
   const int tid = blockIdx.x * blockDim.x + threadIdx.x;
   const int stride = gridDim.x * blockDim.x;
   const bool vec = ((reinterpret_cast<uintptr_t>(succ) | reinterpret_cast<uintptr_t>(copy)) & 15) == 0;
@@ -125,6 +130,7 @@ __global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restr
       tails += tail;
       bad |= (!tail & !range);
       acc += (!tail & range) ? (unsigned long long)s : 0ull;
+      near += (!tail & range) & ((unsigned)(s - (i + t) + kNear) <= 2u * kNear);
     }
   }
   for (int i = (n4 << 2) + tid; i < n; i += stride) {
@@ -135,18 +141,21 @@ __global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restr
     tails += tail;
     bad |= (!tail & !range);
     acc += (!tail & range) ? (unsigned long long)s : 0ull;
+    near += (!tail & range) & ((unsigned)(s - i + kNear) <= 2u * kNear);
   }
   acc = wave_sum(acc);
   tails = wave_sum(tails);
   bad = wave_sum(bad);
+  near = wave_sum(near);
   // one atomic per workgroup: atomics on a single address serialise
   __shared__ unsigned long long s_acc[256 / kWave];
-  __shared__ int s_tails[256 / kWave], s_bad[256 / kWave];
+  __shared__ int s_tails[256 / kWave], s_bad[256 / kWave], s_near[256 / kWave];
   const int w = threadIdx.x / kWave;
   if (lane_id() == 0) {
     s_acc[w] = acc;
     s_tails[w] = tails;
     s_bad[w] = bad;
+    s_near[w] = near;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -154,10 +163,12 @@ __global__ void __launch_bounds__(256) lr_headfind_single(const int32_t* __restr
       acc += s_acc[i];
       tails += s_tails[i];
       bad += s_bad[i];
+      near += s_near[i];
     }
     if (acc) atomicAdd(lsum, acc);
     if (tails) atomicAdd(ltails, tails);
     if (bad) atomicOr(lerr, kErrRange);
+    if (near && lnear) atomicAdd(lnear, (unsigned long long)near);
   }
 }
 
@@ -234,6 +245,10 @@ struct WalkArgs {
   int L;
   int level;
   int log2B;
+  int log2B_far; // level 0, single list, > 0: the block size used instead of
+                 // 2^log2B when fewer than half the successors are local,
+  int kbits_far; // with these offset bits and cut length
+  int max_walk_far;
   int max_walk;
   int cap;       // cut points this level may create
   int cap_prev;  // cut points the level below could create
@@ -249,7 +264,18 @@ template <bool kLevel0, bool kBatched, bool kPacked>
 __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
   LrCtl* ctl = a.ctl;
   const int N = level_nodes(ctl, a.level, a.L, a.cap_prev);
-  const int log2B = a.log2B;
+  // Splitter spacing for level 0 of a single list chosen on the device from
+  // the head-find pass: when most successors are local (sequential-like
+  // layouts), the lanes of a wave walk neighbouring sublists and share cache
+  // lines, and short sublists (spacing 2^log2B) pay; when they are random,
+  // every step is its own line and fewer, longer sublists (2^log2B_far) make
+  // the final scatter's splitter-rank gathers hit in L2.  The plan is sized
+  // for the smaller spacing.
+  const bool far =
+      kLevel0 && a.log2B_far > 0 && 2ull * ctl->near <= (unsigned long long)N;
+  const int log2B = far ? a.log2B_far : a.log2B;
+  const int kbits = far ? a.kbits_far : a.kbits;
+  const int max_walk = far ? a.max_walk_far : a.max_walk;
   const int r = (int)(((int64_t)N + (1 << log2B) - 1) >> log2B);
   const int head_base = kLevel0 ? 0 : ctl->lv[a.level - 1].r;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl->lv[a.level].r = r;
@@ -370,7 +396,7 @@ __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
         y = in.x;
         w = in.y;
       }
-      if (kLevel0 && kPacked) a.work[x] = (sid << a.kbits) | k;
+      if (kLevel0 && kPacked) a.work[x] = (sid << kbits) | k;
       else store_pair(&a.state[x], sid, k);
       k += w;
       if (tail) {
@@ -379,7 +405,7 @@ __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
       } else if (is_static(y, N, log2B, seed)) {
         store_pair(&a.link_out[sid], y >> log2B, k);
         sid = -1;
-      } else if (++steps >= a.max_walk) {
+      } else if (++steps >= max_walk) {
         const int t = atomicAdd(dyn, 1);
         if (t >= a.cap) {
           errbits |= kErrOverflow;
@@ -590,8 +616,12 @@ __global__ void __launch_bounds__(256) lr_expand0(const int2* __restrict__ state
                                                   const int32_t* __restrict__ srank_up,
                                                   int32_t* rank,
                                                   const int64_t* __restrict__ off, LrCtl* ctl,
-                                                  int L, int cap_here, int kbits) {
+                                                  int L, int cap_here, int kbits_near,
+                                                  int kbits_far) {
   const int N = ctl->lv[0].n;
+  // the walk's choice of packing (see lr_walk), from the same count
+  const int kbits = kbits_far > 0 && 2ull * ctl->near <= (unsigned long long)N ? kbits_far
+                                                                                 : kbits_near;
   const int Nup = level_nodes(ctl, 1, L, cap_here);
   int bad = 0;
   const int stride = gridDim.x * blockDim.x;
@@ -842,6 +872,9 @@ struct Plan {
   bool packed = false;     // level 0 state packed into the output buffer
   int kbits = 0;           // offset bits of the packed state
   int max_walk0 = 0;       // cut length at level 0
+  int log2B_far = 0;       // > 0: level 0 may pick this on the device (see lr_walk),
+  int kbits_far = 0;       // with these offset bits (packed form)
+  int max_walk_far = 0;    // and this cut length
 };
 
 inline int bits_for(int64_t v) {  // bits to hold values 0..v-1
@@ -902,6 +935,31 @@ Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o) {
   }
   p.levels = lv;
   return p;
+}
+
+// Completes a plan made for level-0 spacing kLocalSpacing with the far
+// alternative (see lr_walk): its packing and cut length.  The far sublist ids
+// are fewer, so the offset may take more bits; the cut length may only grow,
+// which keeps the planned cut-point capacity sufficient.
+void add_far_spacing(Plan& p, int64_t n0, int64_t L, int far, int max_walk) {
+  if (far <= 0 || p.levels < 1 || p.algo != PJ_ALGO_RULING_SET) return;
+  const int lg = ilog2(far);
+  const int64_t r = (n0 + (1ll << lg) - 1) >> lg;
+  if (!p.packed) {
+    p.log2B_far = lg;
+    p.max_walk_far = p.max_walk0;
+    return;
+  }
+  for (int kb = bits_for(max_walk); kb >= 4; --kb) {
+    const int mwk = std::min(max_walk, 1 << kb);
+    if (mwk < p.max_walk0) break;
+    if (bits_for(r + L + n0 / mwk + 64) + kb <= 31) {
+      p.log2B_far = lg;
+      p.kbits_far = kb;
+      p.max_walk_far = mwk;
+      return;
+    }
+  }
 }
 
 struct Buffers {
@@ -998,18 +1056,20 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
   const bool want_status = o.validate && !o.d_status;
   if (n0 == 0 && !o.d_status) return PJ_OK;
 
+  int far_spacing = 0;
   {  // ruling-set parameters left at zero come from the tune cache, if tuned
     pj_opts raw;
     pj_opts_init(&raw);
     if (user) raw = *user;
     apply_tuned(raw, n0, L);
-    o.spacing = raw.spacing > 0 ? raw.spacing : list_rank_default_spacing(n0);
+    far_spacing = level0_spacing(raw.spacing, n0, single, &o.spacing);
     o.spacing_up = raw.spacing_up > 0 ? raw.spacing_up : o.spacing_up;
     o.cutoff = raw.cutoff > 0 ? std::min(std::max(raw.cutoff, 64), 16384) : o.cutoff;
     o.max_walk = raw.max_walk > 0 ? std::max(raw.max_walk, 16) : o.max_walk;
     if (raw.block > 0) o.block = std::min(1024, (raw.block + 63) / 64 * 64);
   }
   Plan p = make_plan(n0, L, max_size, o);
+  add_far_spacing(p, n0, L, far_spacing, o.max_walk);
   Buffers b;
   const size_t need = carve(p, L, single, o.validate != 0, want_status, nullptr, &b);
   Workspace ws;
@@ -1038,7 +1098,8 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     if (o.validate || o.d_status) {
       if (single)
         hipLaunchKernelGGL(lr_headfind_single<false>, dim3(grid_for(n / 4 + 1, 256, 1024)),
-                           dim3(256), 0, stream, succ, n, nullptr, b.lsum, b.ltails, b.lerr);
+                           dim3(256), 0, stream, succ, n, nullptr, b.lsum, b.ltails, b.lerr,
+                           nullptr);
       else
         hipLaunchKernelGGL(lr_headfind_batched<false>,
                            dim3(grid_for(n / (kHfChunk * 4) + 1, 256, gcap)), dim3(256), 0,
@@ -1084,7 +1145,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     if (single) {
       auto k = p.packed ? lr_headfind_single<true> : lr_headfind_single<false>;
       hipLaunchKernelGGL(k, dim3(grid_for(n / 4 + 1, 256, 1024)), dim3(256), 0, stream, succ, n,
-                         copy, b.lsum, b.ltails, b.lerr);
+                         copy, b.lsum, b.ltails, b.lerr, &b.ctl->near);
     } else {
       auto k = p.packed ? lr_headfind_batched<true> : lr_headfind_batched<false>;
       hipLaunchKernelGGL(k, dim3(grid_for(n / (kHfChunk * 4) + 1, 256, gcap)), dim3(256), 0,
@@ -1110,6 +1171,9 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
       a.L = Li;
       a.level = lv;
       a.log2B = p.log2B[lv];
+      a.log2B_far = lv == 0 && single ? p.log2B_far : 0;
+      a.kbits_far = p.kbits_far;
+      a.max_walk_far = p.max_walk_far;
       a.max_walk = lv == 0 ? p.max_walk0 : o.max_walk;
       a.cap = p.cap[lv];
       a.cap_prev = lv > 0 ? p.cap[lv - 1] : 0;
@@ -1159,7 +1223,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     }
     tm.mark("expand_up");
     const int g0 = grid_for(n, 256, gcap);
-    void (*ex0)(const int2*, const int32_t*, int32_t*, const int64_t*, LrCtl*, int, int, int);
+    void (*ex0)(const int2*, const int32_t*, int32_t*, const int64_t*, LrCtl*, int, int, int, int);
     if (single) {
       if (o.to_tail) ex0 = p.packed ? lr_expand0<false, true, true> : lr_expand0<false, true, false>;
       else ex0 = p.packed ? lr_expand0<false, false, true> : lr_expand0<false, false, false>;
@@ -1168,7 +1232,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
       else ex0 = p.packed ? lr_expand0<true, false, true> : lr_expand0<true, false, false>;
     }
     hipLaunchKernelGGL(ex0, dim3(g0), dim3(256), 0, stream, b.state[0], b.srank[1], rank, off,
-                       b.ctl, Li, p.cap[0], p.kbits);
+                       b.ctl, Li, p.cap[0], p.kbits, single ? p.kbits_far : 0);
     PJ_HIP(hipGetLastError());
     tm.mark("expand0");
   }
@@ -1235,12 +1299,34 @@ int list_rank_default_spacing(int64_t n) {
   return sp;
 }
 
+// Level-0 spacing actually planned.  A caller's (or tuned) value is used as
+// is.  Otherwise a single list of at least 2^22 nodes is planned with
+// spacing kLocalSpacing and lets the walk switch to the size default on the
+// device when its successors are not local (the returned far spacing);
+// smaller lists and batches use the size default.
+constexpr int kLocalSpacing = 8;
+constexpr int64_t kAdaptiveMin = int64_t(1) << 22;
+
+int level0_spacing(int requested, int64_t n0, bool single, int32_t* planned) {
+  if (requested > 0) {
+    *planned = requested;
+    return 0;
+  }
+  const int dflt = list_rank_default_spacing(n0);
+  if (single && n0 >= kAdaptiveMin) {
+    *planned = kLocalSpacing;
+    return dflt;
+  }
+  *planned = dflt;
+  return 0;
+}
+
 size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single) {
   pj_opts raw;
   pj_opts_init(&raw);
   if (user) raw = *user;
   apply_tuned(raw, n0, L);
-  if (raw.spacing <= 0) raw.spacing = list_rank_default_spacing(n0);
+  (void)level0_spacing(raw.spacing, n0, single, &raw.spacing);
   pj_opts o = resolved_opts(&raw);
   Plan p = make_plan(n0, L, n0, o);
   Buffers b;

@@ -313,3 +313,34 @@ def test_autotune_picks_parameters_and_keeps_results(pj, tmp_path):
     torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy(), oracle.list_rank_batched(bs, boff)[1])
     pj.tune_clear()
+
+
+@pytest.mark.parametrize("local_frac", [0.0, 0.45, 0.55, 1.0])
+def test_layout_locality_choice_keeps_ranks(pj, local_frac):
+    """Lists of 2^22 nodes whose successors are local (the next id) for a
+    given fraction of nodes: the walk picks its level-0 spacing on the device
+    from that fraction, on both sides of the one-half threshold."""
+    n = 1 << 22
+    rng = np.random.default_rng(int(local_frac * 100) + 7)
+    # runs of consecutive ids with geometric lengths (a run continues with
+    # probability local_frac), laid out along the list in random order
+    if local_frac >= 1.0:
+        lengths = np.array([n])
+    else:
+        lengths = rng.geometric(1.0 - local_frac, size=n)
+        lengths = lengths[:np.searchsorted(np.cumsum(lengths), n) + 1]
+        lengths[-1] -= lengths.sum() - n
+    starts = np.concatenate([[0], np.cumsum(lengths)[:-1]])
+    perm = rng.permutation(len(lengths))
+    ls, st = lengths[perm], starts[perm]
+    pos0 = np.concatenate([[0], np.cumsum(ls)[:-1]])
+    order = np.repeat(st, ls) + (np.arange(n) - np.repeat(pos0, ls))
+    succ = np.full(n, -1, np.int32)
+    succ[order[:-1]] = order[1:]
+    idx = np.nonzero(succ >= 0)[0]
+    near = np.mean(np.abs(succ[idx].astype(np.int64) - idx) <= 64)
+    assert abs(near - local_frac) < 0.02
+    got = run(pj, succ)
+    want = np.empty(n, np.int32)
+    want[order] = np.arange(n, dtype=np.int32)
+    assert np.array_equal(got, want)
