@@ -102,9 +102,11 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="headline workload only")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--log2n", type=int, default=26)
-    ap.add_argument("--workload", default="c2u",
-                    choices=["c2u", "c2s", "c2b", "c2u_wyllie", "c1", "c3u", "c3p", "c4"],
-                    help="c2u (default) is the headline; the others time one workload "
+    ap.add_argument("--workload", default="list_uniform",
+                    choices=["list_uniform", "list_sequential", "list_blocked",
+                             "list_uniform_wyllie", "list_uniform_2p20", "cc_uniform",
+                             "cc_planted", "lists_batched_4096"],
+                    help="list_uniform (default) is the headline; the others time one workload "
                          "alone (for profiling) and print its own JSON line")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB int32 tensor three times (a kernel of known "
@@ -131,7 +133,7 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x 256 MiB")
         del a, b
-    if args.workload != "c2u":
+    if args.workload != "list_uniform":
         print(json.dumps(single_workload(torch, pj, dev, args)), flush=True)
         return
 
@@ -242,24 +244,24 @@ def single_workload(torch, pj, dev, args):
     """Time one workload alone; returns its JSON record (phases included)."""
     wl = args.workload
     rec = {"workload": wl, "steps": args.steps, "warmup": args.warmup}
-    if wl in ("c2s", "c2b", "c2u_wyllie", "c1"):
-        n = 1 << (20 if wl == "c1" else args.log2n)
-        if wl == "c2s":
+    if wl.startswith("list_"):
+        n = 1 << (20 if wl == "list_uniform_2p20" else args.log2n)
+        if wl == "list_sequential":
             s = W.sequential_list(n)
-        elif wl == "c2b":
+        elif wl == "list_blocked":
             s = W.blocked_list(n, 4096, W.SEED_BASE + 2)
         else:
-            s = W.random_list(n, W.SEED_BASE + (1 if wl == "c1" else 2))
-        algo = "wyllie" if wl == "c2u_wyllie" else "ruling_set"
+            s = W.random_list(n, W.SEED_BASE + (1 if wl == "list_uniform_2p20" else 2))
+        algo = "wyllie" if wl == "list_uniform_wyllie" else "ruling_set"
         ds = torch.from_numpy(s).to(dev)
         dr = torch.empty_like(ds)
         ms = timed(torch, lambda: pj.list_rank(ds, dr, algo=algo), args.steps, args.warmup)
         _, st = pj.list_rank(ds, dr, algo=algo, return_stats=True)
         rec.update(n=n, algo=algo, ms=round(ms, 4), nodes_per_s=round(n / (ms * 1e-3), 1),
                    phases=st["phases"], levels=st["levels"], level_nodes=st["level_nodes"])
-    elif wl in ("c3u", "c3p"):
+    elif wl in ("cc_uniform", "cc_planted"):
         nv, m = 1 << 22, 1 << 25
-        if wl == "c3u":
+        if wl == "cc_uniform":
             src, dst = W.random_graph(nv, m, W.SEED_BASE + 3)
         else:
             src, dst, _ = W.planted_graph(nv, m, 1024, W.SEED_BASE + 3)
@@ -270,7 +272,7 @@ def single_workload(torch, pj, dev, args):
         _, st = pj.connected_components(ds, dd, nv, lab, return_stats=True)
         rec.update(n=nv, m=m, ms=round(ms, 4), edges_per_s=round(m / (ms * 1e-3), 1),
                    rounds=st["rounds"], phases=st["phases"])
-    else:  # c4
+    else:  # lists_batched_4096
         bs, boff = W.batched_lists(4096, 6, 20, W.SEED_BASE + 4)
         dbs, dboff = torch.from_numpy(bs).to(dev), torch.from_numpy(boff).to(dev)
         dbr = torch.empty_like(dbs)
@@ -290,8 +292,8 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
 
     # Wyllie on the same list
     ms = timed(torch, lambda: pj.list_rank(d_succ, d_rank, algo="wyllie"), steps, 1)
-    ex["c2_uniform_wyllie_nodes_per_s"] = round(n / (ms * 1e-3), 1)
-    ex["c2_uniform_wyllie_ms"] = round(ms, 3)
+    ex[f"list_2p{args.log2n}_uniform_wyllie_nodes_per_s"] = round(n / (ms * 1e-3), 1)
+    ex[f"list_2p{args.log2n}_uniform_wyllie_ms"] = round(ms, 3)
     log(f"wyllie uniform {ms:.3f} ms")
 
     # other layouts
@@ -300,7 +302,7 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
         ds = torch.from_numpy(s).to(dev)
         for algo in ("ruling_set", "wyllie"):
             ms = timed(torch, lambda: pj.list_rank(ds, d_rank, algo=algo), steps, 1)
-            ex[f"c2_{name}_{algo}_nodes_per_s"] = round(n / (ms * 1e-3), 1)
+            ex[f"list_2p{args.log2n}_{name}_{algo}_nodes_per_s"] = round(n / (ms * 1e-3), 1)
             log(f"{name} {algo} {ms:.3f} ms")
         del ds
 
@@ -310,9 +312,9 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
     r1 = torch.empty_like(s1)
     for algo in ("ruling_set", "wyllie"):
         ms = timed(torch, lambda: pj.list_rank(s1, r1, algo=algo), 20, 3)
-        ex[f"c1_{algo}_nodes_per_s"] = round(n1 / (ms * 1e-3), 1)
-        ex[f"c1_{algo}_ms"] = round(ms, 4)
-        log(f"c1 {algo} {ms:.4f} ms")
+        ex[f"list_2p20_uniform_{algo}_nodes_per_s"] = round(n1 / (ms * 1e-3), 1)
+        ex[f"list_2p20_uniform_{algo}_ms"] = round(ms, 4)
+        log(f"2^20 uniform {algo} {ms:.4f} ms")
 
     # components
     nv, m = 1 << 22, 1 << 25
@@ -325,12 +327,12 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
         lab = torch.empty(nv, dtype=torch.int32, device=dev)
         ms = timed(torch, lambda: pj.connected_components(ds, dd, nv, lab), steps, 1)
         _, st = pj.connected_components(ds, dd, nv, lab, return_stats=True)
-        ex[f"c3_{kind}_cc_edges_per_s"] = round(m / (ms * 1e-3), 1)
-        ex[f"c3_{kind}_cc_ms"] = round(ms, 3)
-        ex[f"c3_{kind}_rounds"] = st["rounds"]
-        ex[f"c3_{kind}_frac_of_hbm"] = round(
+        ex[f"cc_2p22_{kind}_cc_edges_per_s"] = round(m / (ms * 1e-3), 1)
+        ex[f"cc_2p22_{kind}_cc_ms"] = round(ms, 3)
+        ex[f"cc_2p22_{kind}_rounds"] = st["rounds"]
+        ex[f"cc_2p22_{kind}_frac_of_hbm"] = round(
             (CC_BYTES_PER_PAIR * m + CC_BYTES_PER_VERTEX * nv) / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
-        ex[f"c3_{kind}_phases_ms"] = {k: round(v, 3) for k, v in st["phases"].items()}
+        ex[f"cc_2p22_{kind}_phases_ms"] = {k: round(v, 3) for k, v in st["phases"].items()}
         log(f"cc {kind} {ms:.3f} ms rounds {st['rounds']}")
         del ds, dd, lab
 
@@ -361,14 +363,14 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
     pj.graph_cache_clear()
     ms_t = timed(torch, graphed, steps, 1)
     pj.graph_cache_clear()
-    ex["c4_total_nodes"] = total
-    ex["c4_batched_ms"] = round(ms_b, 3)
-    ex["c4_batched_graph_ms"] = round(ms_g, 3)
-    ex["c4_batched_graph_tuned_ms"] = round(ms_t, 3)
-    ex["c4_tuned"] = best
-    ex["c4_plain_ms"] = round(ms_p, 3)
-    ex["c4_batched_nodes_per_s"] = round(total / (min(ms_b, ms_g, ms_t) * 1e-3), 1)
-    ex["c4_speedup_batched_vs_plain"] = round(ms_p / min(ms_b, ms_g, ms_t), 3)
+    ex["batch_4096_lists_total_nodes"] = total
+    ex["batch_4096_lists_batched_ms"] = round(ms_b, 3)
+    ex["batch_4096_lists_batched_graph_ms"] = round(ms_g, 3)
+    ex["batch_4096_lists_batched_graph_tuned_ms"] = round(ms_t, 3)
+    ex["batch_4096_lists_tuned"] = best
+    ex["batch_4096_lists_plain_ms"] = round(ms_p, 3)
+    ex["batch_4096_lists_batched_nodes_per_s"] = round(total / (min(ms_b, ms_g, ms_t) * 1e-3), 1)
+    ex["batch_4096_lists_speedup_batched_vs_plain"] = round(ms_p / min(ms_b, ms_g, ms_t), 3)
     log(f"batched {ms_b:.3f} ms graph {ms_g:.3f} ms tuned {ms_t:.3f} ms {best} "
         f"plain {ms_p:.3f} ms")
     del dbs, dboff, dbr, views
@@ -452,9 +454,9 @@ def run_serving(torch, pj, args):
     log(f"serving saturation {sat['req_per_s']:.1f} req/s; open loop at {lam:.1f} req/s")
     run = serve_run(torch, S, pool, 600, lam, 3, 16 << 30)
     small = serve_run(torch, S, pool, 200, lam, 4, 512 << 20)
-    ex["c5_saturation_req_per_s"] = round(sat["req_per_s"], 1)
-    ex["c5_rate_req_per_s"] = round(lam, 1)
-    for tag, st in (("c5", run), ("c5_budget512MiB", small)):
+    ex["serving_saturation_req_per_s"] = round(sat["req_per_s"], 1)
+    ex["serving_rate_req_per_s"] = round(lam, 1)
+    for tag, st in (("serving", run), ("serving_512MiB", small)):
         ex[f"{tag}_p50_ms"] = round(st["p50_ms"], 3)
         ex[f"{tag}_p99_ms"] = round(st["p99_ms"], 3)
         ex[f"{tag}_req_per_s"] = round(st["req_per_s"], 1)
