@@ -160,12 +160,19 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
 // in cache, instead of gathers over the whole parent array every round.
 // Pairs whose two parents agree lie inside one tree for good (trees only
 // merge) and are dropped.  The survivors are exactly the parents steps 2 and
-// 3 need.  In round 1 every vertex is its own parent: the input pairs are
-// range-checked and copied without reading D.  D is not written while this
-// kernel runs: step 2 may hook one root twice (arbitrary winner), and a drop
-// decided between two such writes could rest on a parent the second write
-// replaces.  A workgroup reserves room for the survivors of each chunk of
-// kCompactPer * 256 pairs with one atomic.
+// 3 need.  After round 1, D is not written while this kernel runs: step 2
+// may hook one root twice (arbitrary winner), and a drop decided between two
+// such writes could rest on a parent the second write replaces.  A workgroup
+// reserves room for the survivors of each chunk of kCompactPer * 256 pairs
+// with one atomic.
+//
+// Round 1 (kFirst) is this kernel alone.  Every vertex is its own parent,
+// so the input pairs are range-checked and copied without reading D; and
+// every vertex is the root of a star, so step 2 has every pair (a > b) hook
+// D[a] = b (concurrent writes, arbitrary winner) and stamp Q[b].  Then every
+// vertex with a pair is hooked (the larger end of one) or stamped (the
+// smaller end), step 3 finds no stagnant root, and the stamps are never read:
+// the kernel only stores the hooks, one per root and workgroup.
 constexpr int kCompactPer = 8;
 constexpr int kCompactWaves = 256 / kWave;
 // After round 1 a workgroup also drops repeats within its chunk: contracted
@@ -182,15 +189,18 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
                                                   const int32_t* __restrict__ dst,
                                                   const int2* __restrict__ pin, int64_t m_host,
                                                   const unsigned long long* m_dev,
-                                                  const int32_t* __restrict__ D, int n,
+                                                  int32_t* __restrict__ D, int n,
                                                   int2* __restrict__ pout,
-                                                  unsigned long long* m_out, const int32_t* w,
-                                                  int s, CcCtl* ctl) {
+                                                  unsigned long long* m_out, int32_t* w, int s,
+                                                  CcCtl* ctl) {
   if (converged(w, s)) return;
   const int64_t m = kFirst ? m_host : (int64_t)*m_dev;
   __shared__ int cnt[kCompactPer][kCompactWaves];
   __shared__ unsigned long long chunk_base;
   __shared__ unsigned long long seen[kFirst ? 1 : kDedupSlots];
+  __shared__ int hooked_a[kFirst ? kClaim : 1];
+  if (kFirst) claim_clear(hooked_a);
+  bool hooked = false;
   const int wave = threadIdx.x / kWave;
   const int64_t chunk = 256 * kCompactPer;
   bool bad = false;
@@ -215,6 +225,11 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
             du[t] = u;
             dv[t] = v;
             keep[t] = u != v;
+            if (keep[t]) {
+              const int a = u > v ? u : v;
+              if (claim(hooked_a, a)) publish(&D[a], u > v ? v : u);
+              hooked = true;
+            }
           }
         } else {
           const int2 p = pin[e];
@@ -267,6 +282,7 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
     __syncthreads();
   }
   if (kFirst && __ballot(bad) && lane_id() == 0) atomicOr(&ctl->err, kErrRange);
+  if (kFirst) raise_flag(&w[s], hooked);
 }
 
 // Pair kernels take kPairsPer pairs per thread per iteration, issuing all
@@ -274,8 +290,7 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
 constexpr int kPairsPer = 8;
 
 // Step 2 over the surviving pairs: the parents the compaction read at the
-// start of the step.  In round 1 no tree is a non-star, so NS is not read.
-template <bool kFirst>
+// start of the step (rounds 2 and later; round 1 is done by the compaction).
 __global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ pairs,
                                                const unsigned long long* m_dev,
                                                int32_t* __restrict__ D,
@@ -303,15 +318,14 @@ __global__ void __launch_bounds__(256) sv_hook(const int2* __restrict__ pairs,
 #pragma unroll
     for (int t = 0; t < kPairsPer; ++t) {
       // A thread that loses the claim acts as if it had seen a hooked already;
-      // after round 1 the winner re-reads D[a] at the coherent level first,
-      // since late in a solve thousands of workgroups hook the same few roots
-      // (in round 1 a root is the larger end of only ~m/n pairs).
-      if (a[t] >= 0 && da[t] == a[t] && (kFirst || NS[a[t]] != s) && claim(hooked_a, a[t]) &&
-          (kFirst || load_coherent(&D[a[t]]) == a[t])) {
+      // the winner re-reads D[a] at the coherent level first, since late in a
+      // solve thousands of workgroups hook the same few roots.
+      if (a[t] >= 0 && da[t] == a[t] && NS[a[t]] != s && claim(hooked_a, a[t]) &&
+          load_coherent(&D[a[t]]) == a[t]) {
         // Q[a] is not stamped: a hooked root is no root any more, so it is
         // never tested for stagnation
         publish(&D[a[t]], b[t]);
-        if (Q[b[t]] != s && claim(stamped_b, b[t]) && (kFirst || load_coherent(&Q[b[t]]) != s))
+        if (Q[b[t]] != s && claim(stamped_b, b[t]) && load_coherent(&Q[b[t]]) != s)
           publish(&Q[b[t]], s);
         hooked = true;
       }
@@ -624,18 +638,16 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
                              (const int32_t*)nullptr, (const int32_t*)nullptr,
                              (const int2*)b.pairs[(s - 1) & 1], m, b.mcount + (s - 1), D, ni,
                              out, b.mcount + s, b.w, s, b.ctl);
-        if (s == 1)
-          hipLaunchKernelGGL(sv_hook<true>, dim3(gp), dim3(256), 0, stream, (const int2*)out,
+        if (s > 1) {  // round 1's steps 2 and 3 are done by its compaction
+          hipLaunchKernelGGL(sv_hook, dim3(gp), dim3(256), 0, stream, (const int2*)out,
                              b.mcount + s, D, b.NS, b.Q, b.w, s);
-        else
-          hipLaunchKernelGGL(sv_hook<false>, dim3(gp), dim3(256), 0, stream, (const int2*)out,
-                             b.mcount + s, D, b.NS, b.Q, b.w, s);
-        hipLaunchKernelGGL(sv_stagnant_roots, dim3(gv), dim3(256), 0, stream, (const int32_t*)D,
-                           (const int32_t*)b.NS, (const int32_t*)b.Q, ni, b.stag_bits,
-                           b.stag_any, b.w, s);
-        hipLaunchKernelGGL(sv_stagnant, dim3(gp), dim3(256), 0, stream, (const int2*)out,
-                           b.mcount + s, D, (const uint64_t*)b.stag_bits,
-                           (const int32_t*)b.stag_any, b.w, s);
+          hipLaunchKernelGGL(sv_stagnant_roots, dim3(gv), dim3(256), 0, stream,
+                             (const int32_t*)D, (const int32_t*)b.NS, (const int32_t*)b.Q, ni,
+                             b.stag_bits, b.stag_any, b.w, s);
+          hipLaunchKernelGGL(sv_stagnant, dim3(gp), dim3(256), 0, stream, (const int2*)out,
+                             b.mcount + s, D, (const uint64_t*)b.stag_bits,
+                             (const int32_t*)b.stag_any, b.w, s);
+        }
       }
       hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, b.w, s);
     }
