@@ -74,8 +74,11 @@ typedef struct pj_opts {
     int32_t block;            /* threads per workgroup, multiple of 64 in [64, 1024] */
     int32_t spacing;          /* ruling set, first level: one splitter per `spacing`
                                  consecutive node ids (power of two, 2..65536);
-                                 zero: 16, 32 or 64 as n grows past 2^24, 2^25 */
-    int32_t spacing_up;       /* ruling set, recursion levels: same meaning */
+                                 zero: 8, 16, 32 or 64 as n grows past 2^23,
+                                 2^24, 2^25 (a single list of >= 2^24 nodes
+                                 keeps 8 when most successors are local) */
+    int32_t spacing_up;       /* ruling set, recursion levels: same meaning
+                                 (zero: 4) */
     int32_t cutoff;           /* ruling set: a level with at most this many nodes is ranked
                                  by one workgroup in LDS (64..16384) */
     int32_t max_walk;         /* ruling set: a sublist walk is cut after this many nodes,

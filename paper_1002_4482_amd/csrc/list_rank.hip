@@ -1291,10 +1291,10 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
 
 // First-level splitter spacing when the caller leaves it at zero: about 2^20
 // splitters, so the splitter ranks that the final scatter gathers (4 B each)
-// stay near one XCD's 4 MiB L2, between 16 (short walks for small,
+// stay near one XCD's 4 MiB L2, between 8 (short walks for small,
 // latency-bound lists) and 64 (longer walks only add imbalance).
 int list_rank_default_spacing(int64_t n) {
-  int sp = 16;
+  int sp = 8;
   while (sp < 64 && (n >> 20) > sp) sp *= 2;
   return sp;
 }
@@ -1313,7 +1313,7 @@ int level0_spacing(int requested, int64_t n0, bool single, int32_t* planned) {
     return 0;
   }
   const int dflt = list_rank_default_spacing(n0);
-  if (single && n0 >= kAdaptiveMin) {
+  if (single && n0 >= kAdaptiveMin && dflt != kLocalSpacing) {
     *planned = kLocalSpacing;
     return dflt;
   }

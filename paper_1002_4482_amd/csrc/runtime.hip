@@ -151,7 +151,7 @@ pj_opts resolved_opts(const pj_opts* in) {
   o.block = (o.block + 63) / 64 * 64;
   if (o.block > 1024) o.block = 1024;
   if (o.spacing <= 0) o.spacing = 16;
-  if (o.spacing_up <= 0) o.spacing_up = 8;
+  if (o.spacing_up <= 0) o.spacing_up = 4;
   if (o.cutoff <= 0) o.cutoff = 16384;
   if (o.cutoff < 64) o.cutoff = 64;
   if (o.cutoff > 16384) o.cutoff = 16384;
