@@ -24,7 +24,8 @@
 // Each pair is processed in both orientations by the thread that reads it.
 // Before step 2 a compaction kernel replaces every pair by the pair of its
 // ends' parents and drops it when the two agree (see sv_compact); steps 2
-// and 3 read the survivors.  Round 1 starts from D = identity and skips 1a.
+// and 3 read the survivors.  Round 1 starts from D = identity, skips 1a,
+// and does steps 2 and 3 inside its compaction (see sv_compact).
 // Concurrent writes to one root land in arbitrary order; every outcome is
 // one the arbitrary-CRCW algorithm allows: step 2 only hooks star roots onto
 // strictly smaller ids, step 3 only hooks stars that no step-2 hook touched,
