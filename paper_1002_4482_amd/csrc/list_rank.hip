@@ -260,6 +260,8 @@ struct WalkArgs {
 // head-find pass, and each visited slot is overwritten with the node's packed
 // state.  The read and the write then touch the same cache line, which costs
 // far less than a write to a second random line.
+constexpr int kWalkBurst = 16;
+
 template <bool kLevel0, bool kBatched, bool kPacked>
 __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
   LrCtl* ctl = a.ctl;
@@ -373,7 +375,10 @@ __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
       }
     }
     if (__ballot(!retired) == 0) break;
-    if (sid >= 0) {
+    // Up to kWalkBurst steps before looking for new work: when the steps hit
+    // in cache (local layouts) the work-distribution code, not memory, would
+    // otherwise set the pace; random layouts do not notice either way.
+    for (int rep = 0; rep < kWalkBurst && sid >= 0; ++rep) {
       int y, w;
       bool tail;
       if (kLevel0) {
