@@ -71,7 +71,8 @@ typedef struct ihipStream_t *pj_stream_t;
  * need; every zero field means "library default / tuned value". */
 typedef struct pj_opts {
     int32_t algo;             /* PJ_ALGO_* */
-    int32_t block;            /* threads per workgroup, multiple of 64 in [64, 1024] */
+    int32_t block;            /* threads per workgroup of the sublist walks and of Wyllie's
+                                 kernels, multiple of 64 in [64, 1024] (zero: 256) */
     int32_t spacing;          /* ruling set, first level: one splitter per `spacing`
                                  consecutive node ids (power of two, 2..65536);
                                  zero: 8, 16, 32 or 64 as n grows past 2^23,
