@@ -460,24 +460,46 @@ __global__ void __launch_bounds__(kBaseThreads) lr_base_lds(const int2* __restri
   }
   for (int j = tid; j < N; j += kBaseThreads) lnk[j] = -1;
   __syncthreads();
+  // All global loads of a phase are issued before any is used: one
+  // workgroup alone cannot hide their latency otherwise.
   unsigned long long mytotal = 0;
-  for (int j = tid; j < N; j += kBaseThreads) {
-    const int2 in = link[j];
-    mytotal += (unsigned)in.y;
-    if (in.x >= 0 && in.x < N) {
-      if (atomicExch(&lnk[in.x], j) != -1) bad = 1;
-    } else if (in.x != -1) {
-      bad = 1;
+  {
+    int2 in[kPerThread];
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = tid + t * kBaseThreads;
+      in[t] = j < N ? link[j] : make_int2(-1, 0);
+    }
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = tid + t * kBaseThreads;
+      if (j >= N) continue;
+      mytotal += (unsigned)in[t].y;
+      if (in[t].x >= 0 && in[t].x < N) {
+        if (atomicExch(&lnk[in[t].x], j) != -1) bad = 1;
+      } else if (in[t].x != -1) {
+        bad = 1;
+      }
     }
   }
   __syncthreads();
   int myheads = 0;
-  for (int j = tid; j < N; j += kBaseThreads) {
-    const int p = lnk[j];
-    pre[j] = p >= 0 ? link[p].y : 0;
-    if (p < 0) {
-      ++myheads;
-      if (j < head_base || j >= head_base + L) bad = 1;
+  {
+    int pw[kPerThread];
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = tid + t * kBaseThreads;
+      const int p = j < N ? lnk[j] : -1;
+      pw[t] = p >= 0 ? link[p].y : 0;
+      if (j < N && p < 0) {
+        ++myheads;
+        if (j < head_base || j >= head_base + L) bad = 1;
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = tid + t * kBaseThreads;
+      if (j < N) pre[j] = pw[t];
     }
   }
   if (myheads) atomicAdd(&nheads, myheads);
