@@ -196,11 +196,23 @@ int pj_tune_list_rank(const int32_t* succ, const int64_t* offsets, int64_t L,
   if (L < 1 || (!single && !h_offsets)) return PJ_EINVAL;
   const int64_t n0 = single ? n : h_offsets[L];
   if (n0 < 0 || n0 >= INT32_MAX || (n0 > 0 && !succ)) return PJ_EINVAL;
-  int32_t* out = nullptr;
-  PJ_HIP(hipMallocAsync((void**)&out, (size_t)std::max<int64_t>(n0, 1) * 4, s));
-  hipEvent_t e0, e1;
-  PJ_HIP(hipEventCreate(&e0));
-  PJ_HIP(hipEventCreate(&e1));
+  // scratch output and timing events, released on every return path
+  struct Scratch {
+    hipStream_t s;
+    int32_t* out = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    ~Scratch() {
+      if (out) (void)hipFreeAsync(out, s);
+      (void)hipStreamSynchronize(s);
+      if (e0) (void)hipEventDestroy(e0);
+      if (e1) (void)hipEventDestroy(e1);
+    }
+  } scratch{s};
+  PJ_HIP(hipMallocAsync((void**)&scratch.out, (size_t)std::max<int64_t>(n0, 1) * 4, s));
+  PJ_HIP(hipEventCreate(&scratch.e0));
+  PJ_HIP(hipEventCreate(&scratch.e1));
+  int32_t* out = scratch.out;
+  hipEvent_t e0 = scratch.e0, e1 = scratch.e1;
   // Coordinate descent from the library defaults: first-level spacing, then
   // recursion spacing, LDS cutoff and workgroup size, each swept with the
   // others held at their best so far (1 warm-up and 3 timed solves each).
@@ -247,10 +259,6 @@ int pj_tune_list_rank(const int32_t* succ, const int64_t* offsets, int64_t L,
     }
   }
   const pj::Tuned bestt = cur;
-  (void)hipFreeAsync(out, s);
-  (void)hipStreamSynchronize(s);
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
   if (rc != PJ_OK) return rc;
   {
     std::lock_guard<std::mutex> lk(pj::g_tune_mu);

@@ -631,9 +631,10 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
   PJ_HIP(hipGetLastError());
   tm.mark("sv0_init");
 
-  // host-visible copy of the change flag, one pinned word per host thread
-  static thread_local int32_t* hflag = nullptr;
-  if (!hflag) PJ_HIP(hipHostMalloc((void**)&hflag, sizeof(int32_t), hipHostMallocDefault));
+  // host-visible copy of the change flag
+  PinnedWord pinned;
+  int32_t* hflag = pinned.get();
+  if (!hflag) return PJ_ENOMEM;
   int rounds = 0;
   bool done = n == 0;
   int result = PJ_OK;

@@ -60,12 +60,22 @@ int persistent_grid(const void* kernel, int block, size_t lds_bytes);
 // ---------------------------------------------------------------- workspace
 // A bump allocator over one device buffer, either the caller's or one taken
 // stream-ordered from the device memory pool for the duration of the call.
+// Bump allocator over one workspace.  A workspace the library allocated is
+// freed (stream-ordered) by workspace_release, or by the destructor when an
+// error path returns early.
 struct Workspace {
   char* base = nullptr;
   size_t size = 0;
   size_t used = 0;
   bool owned = false;
   hipStream_t stream = nullptr;
+
+  Workspace() = default;
+  Workspace(const Workspace&) = delete;
+  Workspace& operator=(const Workspace&) = delete;
+  ~Workspace() {
+    if (owned && base) (void)hipFreeAsync(base, stream);
+  }
 
   template <typename T>
   T* take(size_t count) {
@@ -82,6 +92,21 @@ inline size_t ws_bytes(size_t count, size_t elem) { return (count * elem + 255) 
 
 int workspace_acquire(Workspace& ws, size_t bytes, const pj_opts* opts, hipStream_t stream);
 int workspace_release(Workspace& ws);
+
+// One pinned host word for a device-to-host flag copy, from a process-wide
+// pool (released on destruction; the pool never shrinks, and holds as many
+// words as calls ever ran at once).
+class PinnedWord {
+ public:
+  PinnedWord();
+  ~PinnedWord();
+  PinnedWord(const PinnedWord&) = delete;
+  PinnedWord& operator=(const PinnedWord&) = delete;
+  int32_t* get() const { return p_; }
+
+ private:
+  int32_t* p_ = nullptr;
+};
 
 // ------------------------------------------------------------ phase timing
 struct PhaseTimer {

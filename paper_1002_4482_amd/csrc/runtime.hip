@@ -105,6 +105,28 @@ int workspace_release(Workspace& ws) {
   return PJ_OK;
 }
 
+// Pinned words are carved from 4 KiB pinned pages that are never freed (a
+// flag copy must not wait for the allocation of a page).
+static std::mutex g_pin_mu;
+static std::vector<int32_t*> g_pin_free;
+
+PinnedWord::PinnedWord() {
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  if (g_pin_free.empty()) {
+    int32_t* page = nullptr;
+    if (hipHostMalloc((void**)&page, 4096, hipHostMallocDefault) != hipSuccess) return;
+    for (int i = 0; i < 4096 / 64; ++i) g_pin_free.push_back(page + i * 16);  // 64 B apart
+  }
+  p_ = g_pin_free.back();
+  g_pin_free.pop_back();
+}
+
+PinnedWord::~PinnedWord() {
+  if (!p_) return;
+  std::lock_guard<std::mutex> lk(g_pin_mu);
+  g_pin_free.push_back(p_);
+}
+
 int PhaseTimer::begin(bool enable, hipStream_t s) {
   on = enable;
   stream = s;
