@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 
+import numpy as np
 import torch
 
 from . import _lib
@@ -33,6 +34,21 @@ def _dev_i64(t, name):
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
     return t
+
+
+def _host_i64(a, length, name):
+    """Host int64 table of exactly `length` entries (None passes through)."""
+    if a is None:
+        return None
+    a = np.ascontiguousarray(a, dtype=np.int64)
+    if a.ndim != 1 or a.shape[0] != length:
+        raise ValueError(f"{name} must hold {length} int64 entries")
+    return a
+
+
+def _need(t, count, name):
+    if t.numel() < count:
+        raise ValueError(f"{name} holds {t.numel()} elements, {count} needed")
 
 
 def _ptr(t):
@@ -84,6 +100,7 @@ def list_rank(succ, rank=None, *, stream=None, return_stats=False, **kw):
     if rank is None:
         rank = torch.empty_like(succ)
     _dev_i32(rank, "rank")
+    _need(rank, n, "rank")
     st = PjStats() if return_stats else None
     o = make_opts(stats=st, **kw)
     rc = _lib.load().pj_list_rank_ex(_ptr(succ), n, _ptr(rank), ctypes.byref(o), _stream_ptr(stream))
@@ -101,6 +118,10 @@ def list_rank_batched(succ, offsets, rank=None, *, h_offsets=None, stream=None,
     if rank is None:
         rank = torch.empty_like(succ)
     _dev_i32(rank, "rank")
+    _need(rank, succ.numel(), "rank")
+    h_offsets = _host_i64(h_offsets, L + 1, "h_offsets")
+    if h_offsets is not None and h_offsets[-1] > succ.numel():
+        raise ValueError("offsets exceed succ")
     st = PjStats() if return_stats else None
     o = make_opts(stats=st, h_offsets=h_offsets, **kw)
     rc = _lib.load().pj_list_rank_batched_ex(_ptr(succ), _ptr(offsets), L, _ptr(rank),
@@ -135,10 +156,17 @@ def connected_components_batched(src, dst, vtx_off, edge_off, label=None, *, h_v
     vtx_off = _dev_i64(vtx_off, "vtx_off")
     edge_off = _dev_i64(edge_off, "edge_off")
     G = vtx_off.numel() - 1
+    if edge_off.numel() != G + 1:
+        raise ValueError("vtx_off and edge_off differ in length")
+    h_vtx_off = _host_i64(h_vtx_off, G + 1, "h_vtx_off")
+    h_edge_off = _host_i64(h_edge_off, G + 1, "h_edge_off")
+    total = int(h_vtx_off[-1]) if h_vtx_off is not None else int(vtx_off[-1].item())
     if label is None:
-        total = int(h_vtx_off[-1]) if h_vtx_off is not None else int(vtx_off[-1].item())
         label = torch.empty(total, dtype=torch.int32, device=src.device)
     _dev_i32(label, "label")
+    _need(label, total, "label")
+    if h_edge_off is not None and h_edge_off[-1] > src.numel():
+        raise ValueError("edge offsets exceed the pair arrays")
     st = PjStats() if return_stats else None
     o = make_opts(stats=st, h_offsets=h_vtx_off, h_edge_offsets=h_edge_off, **kw)
     rc = _lib.load().pj_connected_components_batched_ex(
@@ -162,6 +190,9 @@ def tune_list_rank(succ, offsets=None, *, h_offsets=None, stream=None):
         offsets = _dev_i64(offsets, "offsets")
         if h_offsets is None:
             h_offsets = offsets.cpu().numpy()
+        h_offsets = _host_i64(h_offsets, offsets.numel(), "h_offsets")
+        if h_offsets[-1] > succ.numel():
+            raise ValueError("offsets exceed succ")
         rc = lib.pj_tune_list_rank(_ptr(succ), _ptr(offsets), offsets.numel() - 1,
                                    ctypes.c_void_p(h_offsets.ctypes.data), 0, ctypes.byref(best),
                                    ctypes.byref(ms), _stream_ptr(stream))

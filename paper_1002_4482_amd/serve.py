@@ -20,12 +20,14 @@ def _host_i32(a, name):
     try:
         import torch
         if isinstance(a, torch.Tensor):
-            if a.is_cuda or a.dtype != torch.int32 or not a.is_contiguous():
-                raise TypeError(f"{name}: contiguous int32 CPU tensor expected")
+            if a.is_cuda or a.dtype != torch.int32 or not a.is_contiguous() or a.dim() != 1:
+                raise TypeError(f"{name}: contiguous 1-D int32 CPU tensor expected")
             return a, a.data_ptr()
     except ImportError:
         pass
     a = np.ascontiguousarray(a, dtype=np.int32)
+    if a.ndim != 1:
+        raise ValueError(f"{name}: 1-D array expected")
     return a, a.ctypes.data
 
 

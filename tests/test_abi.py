@@ -7,6 +7,7 @@ import os
 import re
 import subprocess
 
+import numpy as np
 import pytest
 
 from conftest import ROOT
@@ -93,3 +94,19 @@ def test_struct_layout_matches_ctypes(tmp_path):
                        check=True)
         got = int(subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout)
         assert got == want, (s, f, got, want)
+
+
+def test_python_layer_rejects_short_outputs_and_bad_tables():
+    """Argument checks in the Python binding that keep the library from
+    writing past a caller's buffer (run on the CPU: the checks come before any
+    device call)."""
+    torch = pytest.importorskip("torch")
+    from paper_1002_4482_amd import api
+    with pytest.raises(ValueError):
+        api._host_i64(np.zeros(3, np.int64), 4, "h")
+    with pytest.raises(ValueError):
+        api._host_i64(np.zeros((2, 2), np.int64), 4, "h")
+    assert api._host_i64([0, 1, 5], 3, "h").dtype == np.int64
+    with pytest.raises(ValueError):
+        api._need(torch.empty(3, dtype=torch.int32), 4, "rank")
+    api._need(torch.empty(4, dtype=torch.int32), 4, "rank")
