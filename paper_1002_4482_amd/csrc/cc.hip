@@ -59,25 +59,8 @@ struct CcCtl {
 // after the pairs that joined it were dropped, splitting a component.  The
 // shortcut's store stays plain: each word has one writer, and losing it would
 // only leave an older ancestor in place.
-__device__ __forceinline__ void publish(int32_t* p, int32_t v) {
-  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Device-scope relaxed load: sees what `publish` wrote from any XCD.
-__device__ __forceinline__ int32_t load_coherent(const int32_t* p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-// Raises a per-round flag (change or stagnant-root flag) from a workgroup-
-// wide OR.  Thousands of waves raise the same word in one kernel; a
-// write-through store per wave would serialise on that word, so a workgroup
-// stores at most once, and not at all once a coherent load shows it set.
-// Every thread of the workgroup must call it.
-__device__ __forceinline__ void raise_flag(int32_t* flag, bool mine) {
-  if (__syncthreads_or(mine) && threadIdx.x == 0 &&
-      __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
-    publish(flag, 1);
-}
+// `publish`, `load_coherent` and `raise_flag` (the shared device helpers)
+// implement this discipline.
 
 // The round-s kernels do nothing once an earlier round saw no change.
 __device__ __forceinline__ bool converged(const int32_t* w, int s) { return s > 1 && w[s - 1] == 0; }

@@ -196,4 +196,27 @@ __device__ __forceinline__ int find_instance(const int64_t* __restrict__ off, in
   return lo;
 }
 
+// Device-scope relaxed atomic store: written through to the device-coherent
+// level, so a store from one XCD is not lost behind another XCD's
+// write-back L2 when several workgroups write the same word.
+__device__ __forceinline__ void publish(int32_t* p, int32_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-scope relaxed load: sees what `publish` wrote from any XCD.
+__device__ __forceinline__ int32_t load_coherent(const int32_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Raises a per-round flag (change or stagnant-root flag) from a workgroup-
+// wide OR.  Thousands of waves raise the same word in one kernel; a
+// write-through store per wave would serialise on that word, so a workgroup
+// stores at most once, and not at all once a coherent load shows it set.
+// Every thread of the workgroup must call it.
+__device__ __forceinline__ void raise_flag(int32_t* flag, bool mine) {
+  if (__syncthreads_or(mine) && threadIdx.x == 0 &&
+      __hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0)
+    publish(flag, 1);
+}
+
 }  // namespace pj

@@ -75,6 +75,7 @@ def test_paper_tail_convention_and_to_tail(pj):
     dict(spacing=1024), dict(max_walk=16), dict(cutoff=64), dict(seed=12345),
     dict(block=64), dict(block=512), dict(block=1024, spacing=128),
     dict(spacing=8, cutoff=256, max_walk=20, seed=7),
+    dict(algo="wyllie", block=64), dict(algo="wyllie", block=1024),
 ])
 def test_parameters_do_not_change_ranks(pj, params):
     n = 400_009
@@ -344,3 +345,16 @@ def test_layout_locality_choice_keeps_ranks(pj, local_frac):
     want = np.empty(n, np.int32)
     want[order] = np.arange(n, dtype=np.int32)
     assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("layout", ["uniform", "sequential"])
+def test_wyllie_early_exit_reports_rounds(pj, layout):
+    # the jump rounds stop once no node has a next; the count never exceeds
+    # the doubling bound ceil(log2 n), and the ranks stay exact
+    n = 300_007
+    succ = W.random_list(n, 17) if layout == "uniform" else W.sequential_list(n)
+    out, st = pj.list_rank(dev(succ), algo="wyllie", return_stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.list_rank(succ))
+    bound = int(np.ceil(np.log2(n)))
+    assert 1 <= st["rounds"] <= bound
