@@ -108,13 +108,18 @@ def main():
                              "cc_planted", "lists_batched_4096"],
                     help="list_uniform (default) is the headline; the others time one workload "
                          "alone (for profiling) and print its own JSON line")
+    ap.add_argument("--serve-requests", type=int, default=5000,
+                    help="requests per load point of the serving sweep")
+    ap.add_argument("--serve-warmup", type=int, default=500,
+                    help="serving warm-up requests (not timed, not checked)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first copy a 256 MiB int32 tensor three times (a kernel of known "
                          "traffic, to scale HBM counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1",
+        print(json.dumps({"error": "one GPU per process: --gpus must be 1 (the library has no "
+                                   "multi-GPU path)",
                           "n_gpus": args.gpus}), flush=True)
         sys.exit(2)
 
@@ -336,6 +341,8 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
         log(f"cc {kind} {ms:.3f} ms rounds {st['rounds']}")
         del ds, dd, lab
 
+    ex.update(cc_families(torch, pj, dev, steps))
+
     # batched lists vs per-list launches
     log("generating 4096 lists, sizes log-uniform in [2^6, 2^20]")
     bs, boff = W.batched_lists(4096, 6, 20, W.SEED_BASE + 4)
@@ -379,6 +386,45 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
     return ex
 
 
+def cc_families(torch, pj, dev, steps, m=8_000_000, comps=64):
+    """The paper's graph families at m = 8M pairs: collections of random lists
+    (degree 1), random k-ary trees, and random components of edge density d.
+    Rounds, time, and device time per round of each step of a round."""
+    fams = [("lists", None)] + [(f"trees_k{k}", k) for k in (2, 3, 4, 6, 8, 12, 16, 20)] + \
+           [(f"components_d{d}", d) for d in (0.001, 0.01)]
+    out = []
+    for i, (name, par) in enumerate(fams):
+        seed = W.SEED_BASE + 6 + i
+        if name == "lists":
+            src, dst, grp = W.list_graph(m + comps, comps, seed, with_groups=True)
+        elif name.startswith("trees"):
+            src, dst, grp = W.random_tree_graph(m + comps, par, comps, seed, with_groups=True)
+        else:
+            src, dst, grp = W.component_density_graph(m, par, comps, seed)
+        nv = grp.shape[0]
+        # expected labels from the construction: the smallest id of each group
+        gmin = np.full(comps, nv, dtype=np.int64)
+        np.minimum.at(gmin, grp.astype(np.int64), np.arange(nv))
+        want = torch.from_numpy(gmin[grp].astype(np.int32)).to(dev)
+        ds, dd = torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev)
+        lab = torch.empty(nv, dtype=torch.int32, device=dev)
+        ms = timed(torch, lambda: pj.connected_components(ds, dd, nv, lab), steps, 1)
+        ok = bool(torch.equal(lab, want))
+        _, st = pj.connected_components(ds, dd, nv, lab, return_stats=True)
+        r = max(1, st["rounds"])
+        per_round = {k: round(v / r, 4) for k, v in st["phases"].items()
+                     if k.startswith("sv") and k != "sv0_init" or k in ("compact", "flag_check")}
+        out.append({"family": name, "n": nv, "m": int(src.shape[0]), "rounds": st["rounds"],
+                    "ms": round(ms, 3), "edges_per_s": round(src.shape[0] / (ms * 1e-3), 1),
+                    "ms_per_round": per_round, "correct": ok})
+        log(f"cc family {name}: n {nv} m {src.shape[0]} rounds {st['rounds']} {ms:.3f} ms "
+            f"correct {ok}")
+        if not ok:
+            raise SystemExit(f"components mismatch on the {name} family")
+        del ds, dd, lab, want
+    return {"cc_families_m8M": out}
+
+
 def serving_pool(seed, lists=24, graphs=12):
     """Distinct inputs drawn from the serving mix, with their oracle results."""
     import oracle
@@ -396,9 +442,10 @@ def serving_pool(seed, lists=24, graphs=12):
     return pool
 
 
-def serve_run(torch, S, pool, count, rate, seed, budget, check=True):
+def serve_run(torch, S, pool, count, rate, seed, budget, check=True, keep=0):
     """Submit `count` requests (70% lists) with Poisson arrivals at `rate`
-    per second (rate None: all at once); returns the server's stats."""
+    per second (rate None: all at once); returns the server's stats, with the
+    first `keep` results under "kept" as (kind, pool index, output)."""
     import threading
     rng = np.random.default_rng(seed)
     picks = [("lr", int(rng.integers(len(pool["lr"])))) if rng.random() < 0.7 else
@@ -425,8 +472,11 @@ def serve_run(torch, S, pool, count, rate, seed, budget, check=True):
         th.join()
         srv.drain()
         bad = []
+        kept = []
         for i, (rid, (kind, j)) in enumerate(zip(ids, picks)):
             st, _, out = srv.wait(rid)
+            if i < keep:
+                kept.append((kind, j, np.array(out, copy=True)))
             want = pool["lr"][j][1] if kind == "lr" else pool["cc"][j][3]
             wrong = int((out != want).sum()) if check and st == 0 else 0
             if st != 0 or wrong:
@@ -436,6 +486,7 @@ def serve_run(torch, S, pool, count, rate, seed, budget, check=True):
     for b in bad:
         log(f"serving mismatch {b}")
     stats["mismatches"] = len(bad)
+    stats["kept"] = kept
     return stats
 
 
@@ -448,13 +499,40 @@ def run_serving(torch, pj, args):
     pool["cc"] = [(torch.from_numpy(a).pin_memory(), torch.from_numpy(b).pin_memory(), n, r)
                   for a, b, n, r in pool["cc"]]
     ex = {}
-    serve_run(torch, S, pool, 40, None, 1, 16 << 30)  # warm-up
+    serve_run(torch, S, pool, args.serve_warmup, None, 1, 16 << 30, check=False)  # warm-up
     sat = serve_run(torch, S, pool, 300, None, 2, 16 << 30)
-    lam = 0.75 * sat["req_per_s"]
-    log(f"serving saturation {sat['req_per_s']:.1f} req/s; open loop at {lam:.1f} req/s")
-    run = serve_run(torch, S, pool, 600, lam, 3, 16 << 30)
-    small = serve_run(torch, S, pool, 200, lam, 4, 512 << 20)
     ex["serving_saturation_req_per_s"] = round(sat["req_per_s"], 1)
+    log(f"serving saturation {sat['req_per_s']:.1f} req/s")
+    # open-loop Poisson arrivals at fractions of the saturation rate; 0.75 is
+    # the headline point
+    sweep = {}
+    for frac in (0.25, 0.5, 0.75, 0.9):
+        lam = frac * sat["req_per_s"]
+        st = serve_run(torch, S, pool, args.serve_requests, lam, 3, 16 << 30,
+                       keep=12 if frac == 0.75 else 0)
+        sweep[frac] = (lam, st)
+        log(f"serving at {frac:.2f} x saturation ({lam:.1f} req/s): p50 {st['p50_ms']:.2f} ms "
+            f"p99 {st['p99_ms']:.2f} ms {st['req_per_s']:.1f} req/s "
+            f"mismatches {st['mismatches']}")
+    ex["serving_sweep"] = [
+        {"load": frac, "rate_req_per_s": round(lam, 1), "p50_ms": round(st["p50_ms"], 3),
+         "p99_ms": round(st["p99_ms"], 3), "req_per_s": round(st["req_per_s"], 1),
+         "completed": st["completed"], "mismatches": st["mismatches"]}
+        for frac, (lam, st) in sweep.items()]
+    lam, run = sweep[0.75]
+    # a sample of served results re-run alone through the plain calls
+    rerun_bad = 0
+    for kind, j, out in run["kept"]:
+        if kind == "lr":
+            d = pool["lr"][j][0].cuda()
+            alone = pj.list_rank(d).cpu().numpy()
+        else:
+            src, dst, n, _ = pool["cc"][j]
+            alone = pj.connected_components(src.cuda(), dst.cuda(), n).cpu().numpy()
+        rerun_bad += int(not np.array_equal(alone, out))
+    ex["serving_rerun_sample"] = len(run["kept"])
+    ex["serving_rerun_mismatches"] = rerun_bad
+    small = serve_run(torch, S, pool, 200, lam, 4, 512 << 20)
     ex["serving_rate_req_per_s"] = round(lam, 1)
     for tag, st in (("serving", run), ("serving_512MiB", small)):
         ex[f"{tag}_p50_ms"] = round(st["p50_ms"], 3)
@@ -469,6 +547,7 @@ def run_serving(torch, pj, args):
         ex[f"{tag}_bytes_peak"] = st["bytes_peak"]
         log(f"{tag}: p50 {st['p50_ms']:.2f} ms p99 {st['p99_ms']:.2f} ms "
             f"{st['req_per_s']:.1f} req/s mismatches {st['mismatches']}")
+    log(f"serving re-run sample: {rerun_bad} of {len(run['kept'])} differ")
     return ex
 
 

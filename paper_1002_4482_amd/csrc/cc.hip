@@ -632,7 +632,9 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
           hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni,
                              (const int32_t*)b.w, s, f, q ? (const int32_t*)(f - 1) : nullptr);
         }
+      tm.mark("sv1a_shortcut");
       hipLaunchKernelGGL(sv_mark, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, b.w, s, b.ctl);
+      tm.mark("sv1b_mark");
       if (m > 0) {
         // round 1 reads the input pairs, later rounds the survivors of the last one
         int2* out = b.pairs[s & 1];
@@ -645,27 +647,31 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
                              (const int32_t*)nullptr, (const int32_t*)nullptr,
                              (const int2*)b.pairs[(s - 1) & 1], m, b.mcount + (s - 1), D, ni,
                              out, b.mcount + s, b.w, s, b.ctl);
+        tm.mark("compact");
         if (s > 1) {  // round 1's steps 2 and 3 are done by its compaction
           hipLaunchKernelGGL(sv_hook, dim3(gp), dim3(256), 0, stream, (const int2*)out,
                              b.mcount + s, D, b.NS, b.Q, b.w, s);
+          tm.mark("sv2_hook");
           hipLaunchKernelGGL(sv_stagnant_roots, dim3(gv), dim3(256), 0, stream,
                              (const int32_t*)D, (const int32_t*)b.NS, (const int32_t*)b.Q, ni,
                              b.stag_bits, b.stag_any, b.w, s);
           hipLaunchKernelGGL(sv_stagnant, dim3(gp), dim3(256), 0, stream, (const int2*)out,
                              b.mcount + s, D, (const uint64_t*)b.stag_bits,
                              (const int32_t*)b.stag_any, b.w, s);
+          tm.mark("sv3_stagnant");
         }
       }
       hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, (const int32_t*)b.w,
                          s, (int32_t*)nullptr, (const int32_t*)nullptr);
+      tm.mark("sv4_shortcut");
     }
     PJ_HIP(hipGetLastError());
     PJ_HIP(hipMemcpyAsync(hflag, b.w + rounds, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
     PJ_HIP(hipStreamSynchronize(stream));
+    tm.mark("flag_check");
     if (*hflag == 0) done = true;
     else if (rounds >= max_rounds) done = true;
   }
-  tm.mark("sv_rounds");
 
   if (n > 0) {
     hipLaunchKernelGGL(canon_init, dim3(gv), dim3(256), 0, stream, b.NS, ni);

@@ -638,6 +638,7 @@ __global__ void __launch_bounds__(256) lr_expand(const int2* __restrict__ state,
 }
 
 // Level 0: write the output ranks (from the head, or to the tail).
+constexpr int kExpandPer = 4;
 template <bool kBatched, bool kToTail, bool kPacked>
 __global__ void __launch_bounds__(256) lr_expand0(const int2* __restrict__ state,
                                                   const int32_t* __restrict__ srank_up,
@@ -651,27 +652,44 @@ __global__ void __launch_bounds__(256) lr_expand0(const int2* __restrict__ state
                                                                                  : kbits_near;
   const int Nup = level_nodes(ctl, 1, L, cap_here);
   int bad = 0;
-  const int stride = gridDim.x * blockDim.x;
-  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N; j += stride) {
-    int2 s;
-    if (kPacked) {
-      const int w = rank[j];
-      s = make_int2((int)((unsigned)w >> kbits), w & ((1 << kbits) - 1));
-    } else {
-      s = state[j];
-    }
-    int v = 0;
-    if ((unsigned)s.x < (unsigned)Nup) v = srank_up[s.x] + s.y;
-    else bad = 1;
-    if (kToTail) {
-      int size = N;
-      if (kBatched) {
-        const int l = find_instance(off, L, j);
-        size = (int)(off[l + 1] - off[l]);
+  // kExpandPer nodes per thread per pass, loads first: the splitter-rank
+  // gathers of one thread are in flight together.  The packed words are read
+  // once and overwritten, so they are streamed past the cache (nontemporal)
+  // and the gathered splitter ranks keep it.
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t j0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j0 < N;
+       j0 += kExpandPer * stride) {
+    int2 s[kExpandPer];
+#pragma unroll
+    for (int u = 0; u < kExpandPer; ++u) {
+      const int64_t j = j0 + u * stride;
+      s[u] = make_int2(-1, 0);
+      if (j < N) {
+        if (kPacked) {
+          const int w = __builtin_nontemporal_load(&rank[j]);
+          s[u] = make_int2((int)((unsigned)w >> kbits), w & ((1 << kbits) - 1));
+        } else {
+          s[u] = state[j];
+        }
       }
-      v = size - 1 - v;
     }
-    __builtin_nontemporal_store(v, &rank[j]);
+#pragma unroll
+    for (int u = 0; u < kExpandPer; ++u) {
+      const int64_t j = j0 + u * stride;
+      if (j >= N) break;
+      int v = 0;
+      if ((unsigned)s[u].x < (unsigned)Nup) v = srank_up[s[u].x] + s[u].y;
+      else bad = 1;
+      if (kToTail) {
+        int size = N;
+        if (kBatched) {
+          const int l = find_instance(off, L, j);
+          size = (int)(off[l + 1] - off[l]);
+        }
+        v = size - 1 - v;
+      }
+      __builtin_nontemporal_store(v, &rank[j]);
+    }
   }
   if (bad) atomicOr(&ctl->err, kErrTotal);
 }

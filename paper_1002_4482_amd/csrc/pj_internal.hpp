@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "ptrjump.h"
 
@@ -109,15 +110,19 @@ class PinnedWord {
 };
 
 // ------------------------------------------------------------ phase timing
+// Device time per named phase.  Each mark closes the interval since the last
+// one and adds it to the phase of that name, so a phase marked once per round
+// or per level accumulates over all of them (at most PJ_MAX_PHASES names).
 struct PhaseTimer {
   bool on = false;
   hipStream_t stream = nullptr;
-  int n = 0;
-  hipEvent_t ev[PJ_MAX_PHASES + 1] = {};
+  int n = 0;                             // distinct phase names
   const char* name[PJ_MAX_PHASES] = {};
+  std::vector<hipEvent_t> ev;            // ev[0] = begin, ev[j + 1] closes mark j
+  std::vector<int> phase_of;             // phase index of mark j
   int begin(bool enable, hipStream_t s);
-  void mark(const char* phase_name);  // closes the current phase
-  int finish(pj_stats* st);           // synchronises, fills phase times
+  void mark(const char* phase_name);
+  int finish(pj_stats* st);              // synchronises, fills phase times
   ~PhaseTimer();
 };
 

@@ -1,5 +1,6 @@
 // Host runtime shared by all entry points: option defaults, error strings,
 // device properties, workspace and phase timers.
+#include <cstring>
 #include <mutex>
 #include <string>
 #include <unordered_map>
@@ -132,27 +133,44 @@ int PhaseTimer::begin(bool enable, hipStream_t s) {
   stream = s;
   n = 0;
   if (!on) return PJ_OK;
-  for (int i = 0; i <= PJ_MAX_PHASES; ++i) PJ_HIP(hipEventCreate(&ev[i]));
-  PJ_HIP(hipEventRecord(ev[0], stream));
+  hipEvent_t e = nullptr;
+  PJ_HIP(hipEventCreate(&e));
+  ev.push_back(e);
+  PJ_HIP(hipEventRecord(e, stream));
   return PJ_OK;
 }
 
 void PhaseTimer::mark(const char* phase_name) {
-  if (!on || n >= PJ_MAX_PHASES) return;
-  name[n] = phase_name;
-  ++n;
-  (void)hipEventRecord(ev[n], stream);
+  if (!on) return;
+  int p = 0;
+  while (p < n && strcmp(name[p], phase_name) != 0) ++p;
+  if (p == n) {
+    if (n >= PJ_MAX_PHASES) return;
+    name[n++] = phase_name;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) {
+    on = false;  // finish() reports what was recorded so far
+    return;
+  }
+  ev.push_back(e);
+  phase_of.push_back(p);
+  (void)hipEventRecord(e, stream);
 }
 
 int PhaseTimer::finish(pj_stats* st) {
-  if (!on) return PJ_OK;
-  PJ_HIP(hipEventSynchronize(ev[n]));
+  if (ev.empty()) return PJ_OK;
+  PJ_HIP(hipEventSynchronize(ev.back()));
   if (st) {
+    float acc[PJ_MAX_PHASES] = {};
+    for (size_t j = 0; j < phase_of.size(); ++j) {
+      float ms = 0.f;
+      PJ_HIP(hipEventElapsedTime(&ms, ev[j], ev[j + 1]));
+      acc[phase_of[j]] += ms;
+    }
     st->nphases = n;
     for (int i = 0; i < n; ++i) {
-      float ms = 0.f;
-      PJ_HIP(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
-      st->phase_ms[i] = ms;
+      st->phase_ms[i] = acc[i];
       snprintf(st->phase_name[i], sizeof st->phase_name[i], "%s", name[i]);
     }
   }
@@ -160,9 +178,7 @@ int PhaseTimer::finish(pj_stats* st) {
 }
 
 PhaseTimer::~PhaseTimer() {
-  if (!on) return;
-  for (int i = 0; i <= PJ_MAX_PHASES; ++i)
-    if (ev[i]) (void)hipEventDestroy(ev[i]);
+  for (hipEvent_t e : ev) (void)hipEventDestroy(e);
 }
 
 pj_opts resolved_opts(const pj_opts* in) {

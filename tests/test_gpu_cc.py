@@ -48,10 +48,13 @@ def test_planted_matches_oracle(pj, n, m, groups):
 
 
 @pytest.mark.parametrize("family", ["lists", "trees2", "trees7", "path_up", "path_down", "star",
-                                    "self_loops"])
+                                    "self_loops", "dense0.001", "dense0.01"])
 def test_graph_families(pj, family):
     n = 100_000
-    if family == "lists":
+    if family.startswith("dense"):
+        src, dst, group_of = W.component_density_graph(400_000, float(family[5:]), 16, 4)
+        n = group_of.shape[0]
+    elif family == "lists":
         src, dst = W.list_graph(n, 37, 1)
     elif family == "trees2":
         src, dst = W.random_tree_graph(n, 2, 11, 2)

@@ -83,6 +83,27 @@ def test_planted_closed_form(n, m, groups, seed):
     check_cc_invariants(src, dst, label)
 
 
+@pytest.mark.parametrize("family", ["lists", "trees1", "trees3", "trees20", "dense0.01",
+                                    "dense0.1"])
+def test_family_closed_form(family):
+    # the paper's graph families carry their components by construction:
+    # label = smallest id of the vertex's list / tree / component
+    if family == "lists":
+        src, dst, group_of = W.list_graph(30_000, 17, 6, with_groups=True)
+    elif family.startswith("trees"):
+        src, dst, group_of = W.random_tree_graph(30_000, int(family[5:]), 9, 7, with_groups=True)
+    else:
+        src, dst, group_of = W.component_density_graph(40_000, float(family[5:]), 13, 8)
+    n = group_of.shape[0]
+    groups = int(group_of.max()) + 1
+    label = oracle.connected_components(src, dst, n)
+    gmin = np.full(groups, n, dtype=np.int64)
+    np.minimum.at(gmin, group_of.astype(np.int64), np.arange(n))
+    assert np.array_equal(label, gmin[group_of].astype(np.int32))
+    assert len(np.unique(label)) == groups
+    check_cc_invariants(src, dst, label)
+
+
 @pytest.mark.parametrize("n,m,seed", [(20000, 9000, 3), (1 << 17, 1 << 18, 4), (3000, 0, 5)])
 def test_scipy_partition_cross_check(n, m, seed):
     src, dst = W.random_graph(n, m, seed)

@@ -28,6 +28,7 @@ from .gen import (  # noqa: F401
     planted_graph,
     list_graph,
     random_tree_graph,
+    component_density_graph,
     density_graph,
     serving_mix,
 )

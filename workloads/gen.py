@@ -20,8 +20,19 @@ Graphs (connected components, Section 4):
                 a multinomial draw proportional to group size, with uniform
                 endpoints inside the group; finally the pair order is shuffled.
 The paper's graph families (Section 4: collections of random lists, random
-trees of degree k, random graphs with edge density d) are `list_graph`,
-`random_tree_graph` and `density_graph`.
+trees of degree k, random graphs made of connected components with edge
+density d) are `list_graph`, `random_tree_graph` and
+`component_density_graph`; `density_graph` is one G(n, m) graph of density d.
+  * list_graph -- a random permutation of the vertices cut at `lists` - 1
+                random places; consecutive vertices of a piece are joined.
+  * random_tree_graph -- `trees` trees of near-equal size, each a complete
+                k-ary tree (position p > 0 attaches to (p - 1) // k) whose
+                positions carry random vertex ids.
+  * component_density_graph -- `comps` components of c vertices, c chosen so
+                that comps * d * c^2 / 2 is about m; each is a random recursive
+                tree plus uniform pairs inside it, up to d * c * (c - 1) / 2
+                pairs; vertex ids dealt by a random permutation, pair order
+                shuffled.
 """
 
 from __future__ import annotations
@@ -45,6 +56,7 @@ __all__ = [
     "list_graph",
     "random_tree_graph",
     "density_graph",
+    "component_density_graph",
     "serving_mix",
 ]
 
@@ -209,19 +221,26 @@ def planted_graph(n: int, m: int, groups: int, seed: int):
     return src[perm], dst[perm], group_of
 
 
-def list_graph(n: int, lists: int, seed: int):
-    """Collection of `lists` random paths over a random split of n vertices."""
+def list_graph(n: int, lists: int, seed: int, with_groups: bool = False):
+    """Collection of `lists` random paths over a random split of n vertices.
+    With `with_groups`, also returns the path index of every vertex."""
     rng = _rng(seed)
     order = rng.permutation(n).astype(np.int32)
     cuts = np.sort(rng.choice(np.arange(1, n), size=max(0, lists - 1), replace=False)) if n > 1 else []
     brk = np.zeros(n, dtype=bool)
     brk[np.asarray(cuts, dtype=np.int64)] = True
     keep = ~brk[1:]
-    return order[:-1][keep].copy(), order[1:][keep].copy()
+    src, dst = order[:-1][keep].copy(), order[1:][keep].copy()
+    if not with_groups:
+        return src, dst
+    group_of = np.empty(n, dtype=np.int32)
+    group_of[order] = np.cumsum(brk).astype(np.int32)
+    return src, dst, group_of
 
 
-def random_tree_graph(n: int, k: int, trees: int, seed: int):
-    """Collection of `trees` random k-ary trees (complete k-ary shape, random labels)."""
+def random_tree_graph(n: int, k: int, trees: int, seed: int, with_groups: bool = False):
+    """Collection of `trees` random k-ary trees (complete k-ary shape, random
+    labels).  With `with_groups`, also returns the tree index of every vertex."""
     rng = _rng(seed)
     labels = rng.permutation(n).astype(np.int64)
     sizes = np.full(trees, n // trees, dtype=np.int64)
@@ -232,7 +251,38 @@ def random_tree_graph(n: int, k: int, trees: int, seed: int):
     pos = np.arange(n, dtype=np.int64) - starts[tid]
     child = pos > 0
     parent_pos = starts[tid[child]] + (pos[child] - 1) // k
-    return labels[child].astype(np.int32), labels[parent_pos].astype(np.int32)
+    src, dst = labels[child].astype(np.int32), labels[parent_pos].astype(np.int32)
+    if not with_groups:
+        return src, dst
+    group_of = np.empty(n, dtype=np.int32)
+    group_of[labels] = tid.astype(np.int32)
+    return src, dst, group_of
+
+
+def component_density_graph(m: int, d: float, comps: int, seed: int):
+    """`comps` connected components of equal size and edge density about d,
+    about m pairs in all.  Returns (src, dst, group_of_vertex int32[n])."""
+    if comps < 1 or not (0.0 < d <= 1.0) or m < 1:
+        raise ValueError("need comps >= 1, 0 < d <= 1 and m >= 1")
+    rng = _rng(seed)
+    c = max(2, int(round(np.sqrt(2.0 * m / (comps * d)))))
+    per = max(c - 1, int(round(d * c * (c - 1) / 2)))
+    n = comps * c
+    members = rng.permutation(n).astype(np.int32)  # component g owns members[g*c:(g+1)*c]
+    group_of = np.empty(n, dtype=np.int32)
+    group_of[members] = np.repeat(np.arange(comps, dtype=np.int32), c)
+    base = np.repeat(np.arange(comps, dtype=np.int64) * c, c - 1)
+    w = np.tile(np.arange(1, c, dtype=np.int64), comps)  # position inside the component
+    parent = base + np.floor(rng.random(w.shape[0]) * w).astype(np.int64)
+    tree_src, tree_dst = members[base + w], members[parent]
+    extra = per - (c - 1)
+    eb = np.repeat(np.arange(comps, dtype=np.int64) * c, extra)
+    u = eb + rng.integers(0, c, size=eb.shape[0])
+    v = eb + rng.integers(0, c, size=eb.shape[0])
+    src = np.concatenate([tree_src, members[u]]).astype(np.int32)
+    dst = np.concatenate([tree_dst, members[v]]).astype(np.int32)
+    perm = rng.permutation(src.shape[0])
+    return src[perm], dst[perm], group_of
 
 
 def density_graph(n: int, d: float, seed: int):
