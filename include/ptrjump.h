@@ -104,7 +104,8 @@ typedef struct pj_stats {
     int32_t levels;               /* ruling set: walk levels (recursion depth) */
     int32_t base_kind;            /* ruling set: 1 LDS workgroup, 2 device-wide pointer jumping */
     int32_t rounds;               /* components: Shiloach-Vishkin rounds run;
-                                     Wyllie: pointer-jumping rounds that did work */
+                                     Wyllie: pointer-jumping rounds, ceil(log2) of the
+                                     longest list */
     int64_t level_nodes[PJ_MAX_LEVELS + 1]; /* nodes at each level (level 0 = input) */
     int32_t nphases;
     char phase_name[PJ_MAX_PHASES][24];

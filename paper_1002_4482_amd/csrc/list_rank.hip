@@ -708,12 +708,9 @@ template <bool kBatched>
 __global__ void __launch_bounds__(1024) wy_init(const int32_t* __restrict__ succ,
                                                 const int64_t* __restrict__ off, int L, int n,
                                                 unsigned long long* __restrict__ pair,
-                                                int32_t* lerr, int32_t* __restrict__ flags,
-                                                int rounds) {
+                                                int32_t* lerr) {
   const int stride = gridDim.x * blockDim.x;
-  const int t = blockIdx.x * blockDim.x + threadIdx.x;
-  if (t > 0 && t < rounds) flags[t] = 0;  // flags[0] is never read
-  for (int g = t; g < n; g += stride) {
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
     int64_t base = 0;
     int size = n, l = 0;
     if (kBatched) {
@@ -732,25 +729,15 @@ __global__ void __launch_bounds__(1024) wy_init(const int32_t* __restrict__ succ
   }
 }
 
-// Round `it` of the jumps.  flags[it] (it >= 1) says whether round it - 1
-// left any node with a next; once one did not, every later round returns at
-// once.  The in-place update often jumps further than doubling, so rounds
-// before the worst-case bound may already finish the job.
-__global__ void __launch_bounds__(1024) wy_jump(unsigned long long* __restrict__ pair, int n,
-                                                int32_t* __restrict__ flags, int it, int rounds) {
-  if (it > 0 && flags[it] == 0) return;  // workgroup-uniform: written by an earlier kernel
+__global__ void __launch_bounds__(1024) wy_jump(unsigned long long* __restrict__ pair, int n) {
   const int stride = gridDim.x * blockDim.x;
-  bool live = false;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
     const unsigned long long v = pair[g];
     const int nx = (int)(unsigned)v;
     if (nx < 0) continue;
     const unsigned long long q = pair[nx];
-    const int nq = (int)(unsigned)q;
-    pair[g] = pack_dn((int)(v >> 32) + (int)(q >> 32), nq);
-    live |= nq >= 0;
+    pair[g] = pack_dn((int)(v >> 32) + (int)(q >> 32), (int)(unsigned)q);
   }
-  if (it + 1 < rounds) raise_flag(&flags[it + 1], live);
 }
 
 template <bool kBatched, bool kToTail>
@@ -1032,7 +1019,6 @@ struct Buffers {
   int32_t* wide_lnk = nullptr;
   unsigned long long* wide_pl = nullptr;
   unsigned long long* wy_pair = nullptr;
-  int32_t* wy_flags = nullptr;
   int32_t* chk = nullptr;
   int32_t* status_tmp = nullptr;
 };
@@ -1055,7 +1041,6 @@ size_t carve(const Plan& p, int64_t L, bool single, bool validate, bool want_sta
   if (want_status) take(b->status_tmp, (size_t)std::max<int64_t>(L, 1));
   if (p.algo == PJ_ALGO_WYLLIE) {
     take(b->wy_pair, (size_t)p.bound[0]);
-    take(b->wy_flags, (size_t)std::max(p.wy_rounds, 1));
     return bytes;
   }
   if (p.small) return bytes;
@@ -1170,14 +1155,13 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     const int g = grid_for(n, blk, gcap);
     if (single)
       hipLaunchKernelGGL(wy_init<false>, dim3(g), dim3(blk), 0, stream, succ, off, Li, n,
-                         b.wy_pair, b.lerr, b.wy_flags, p.wy_rounds);
+                         b.wy_pair, b.lerr);
     else
       hipLaunchKernelGGL(wy_init<true>, dim3(g), dim3(blk), 0, stream, succ, off, Li, n,
-                         b.wy_pair, b.lerr, b.wy_flags, p.wy_rounds);
+                         b.wy_pair, b.lerr);
     tm.mark("wyllie_init");
     for (int it = 0; it < p.wy_rounds; ++it)
-      hipLaunchKernelGGL(wy_jump, dim3(g), dim3(blk), 0, stream, b.wy_pair, n, b.wy_flags, it,
-                         p.wy_rounds);
+      hipLaunchKernelGGL(wy_jump, dim3(g), dim3(blk), 0, stream, b.wy_pair, n);
     tm.mark("wyllie_jump");
     if (single) {
       if (o.to_tail)
@@ -1344,14 +1328,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     st->level_nodes[0] = n0;
     for (int l = 1; l <= p.levels && l <= PJ_MAX_LEVELS; ++l)
       st->level_nodes[l] = hc.lv[l - 1].r + L + std::min(hc.lv[l - 1].dyn, p.cap[l - 1]);
-    if (p.algo == PJ_ALGO_WYLLIE && n0 > 0 && p.wy_rounds > 0) {
-      std::vector<int32_t> hf((size_t)p.wy_rounds);
-      PJ_HIP(hipMemcpyAsync(hf.data(), b.wy_flags, sizeof(int32_t) * p.wy_rounds,
-                            hipMemcpyDeviceToHost, stream));
-      PJ_HIP(hipStreamSynchronize(stream));
-      st->rounds = 1;  // round 0 always runs; round r > 0 runs while flags[r] is set
-      while (st->rounds < p.wy_rounds && hf[(size_t)st->rounds] != 0) ++st->rounds;
-    }
+    if (p.algo == PJ_ALGO_WYLLIE) st->rounds = n0 > 0 ? p.wy_rounds : 0;
     st->status = result;
   }
   PJ_TRY(workspace_release(ws));
