@@ -105,7 +105,7 @@ def main():
     ap.add_argument("--workload", default="list_uniform",
                     choices=["list_uniform", "list_sequential", "list_blocked",
                              "list_uniform_wyllie", "list_uniform_2p20", "cc_uniform",
-                             "cc_planted", "lists_batched_4096"],
+                             "cc_planted", "lists_batched_4096", "list_sweep"],
                     help="list_uniform (default) is the headline; the others time one workload "
                          "alone (for profiling) and print its own JSON line")
     ap.add_argument("--serve-requests", type=int, default=5000,
@@ -249,7 +249,9 @@ def single_workload(torch, pj, dev, args):
     """Time one workload alone; returns its JSON record (phases included)."""
     wl = args.workload
     rec = {"workload": wl, "steps": args.steps, "warmup": args.warmup}
-    if wl.startswith("list_"):
+    if wl == "list_sweep":
+        rec["sizes"] = list_sweep(torch, pj, dev, args)
+    elif wl.startswith("list_"):
         n = 1 << (20 if wl == "list_uniform_2p20" else args.log2n)
         if wl == "list_sequential":
             s = W.sequential_list(n)
@@ -289,6 +291,40 @@ def single_workload(torch, pj, dev, args):
                    levels=st["levels"], level_nodes=st["level_nodes"])
     log(json.dumps(rec))
     return rec
+
+
+def list_sweep(torch, pj, dev, args):
+    """Uniform random lists from 2^20 to 2^28 nodes: where the rate bends as
+    the list outgrows the 256 MiB last-level cache."""
+    rows = []
+    for lg in (20, 22, 24, 25, 26, 27, 28):
+        n = 1 << lg
+        log(f"sweep: generating a uniform list of 2^{lg} nodes")
+        s, order = W.random_list_with_order(n, W.SEED_BASE + 2)
+        ds = torch.from_numpy(s).to(dev)
+        dr = torch.empty_like(ds)
+        del s
+        steps = max(3, min(args.steps, 20 if lg <= 24 else 8))
+        row = {"log2n": lg}
+        do = torch.from_numpy(order).to(dev).long()
+        want = torch.arange(n, dtype=torch.int32, device=dev)
+        del order
+        for algo in ("ruling_set", "wyllie"):
+            ms = timed(torch, lambda: pj.list_rank(ds, dr, algo=algo), steps, 1)
+            _, st = pj.list_rank(ds, dr, algo=algo, return_stats=True)
+            row[f"{algo}_ms"] = round(ms, 4)
+            row[f"{algo}_nodes_per_s"] = round(n / (ms * 1e-3), 1)
+            if algo == "ruling_set":
+                row["walk0_ms"] = round(st["phases"].get("walk0", 0.0), 4)
+                row["expand0_ms"] = round(st["phases"].get("expand0", 0.0), 4)
+            # closed form: the k-th node of the list order has rank k
+            row[f"{algo}_correct"] = bool(torch.equal(dr[do], want))
+        del do, want
+        log(f"sweep 2^{lg}: {row}")
+        rows.append(row)
+        del ds, dr
+        torch.cuda.empty_cache()
+    return rows
 
 
 def run_extras(torch, pj, dev, d_succ, d_rank, n, args):

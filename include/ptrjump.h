@@ -125,7 +125,11 @@ int pj_version(void);
  * node i in [0, n); the tail is marked by succ[i] == -1 or succ[i] == i.
  * Writes rank[i] = distance of node i from the head (rank[head] = 0), or with
  * opts->to_tail the distance to the tail, which is the paper's definition.
- * rank must not alias succ.  n == 0 is a no-op.
+ * rank may be succ itself: the ranks then overwrite the successors in place
+ * (Section 3.2 returns the ranks in the device successor array), and on an
+ * error return the array's contents are unspecified; opts->validate needs
+ * separate arrays (PJ_EINVAL in place).  Any other overlap of rank and succ
+ * is PJ_EINVAL.  n == 0 is a no-op.
  */
 int pj_list_rank(const int32_t *succ, int64_t n, int32_t *rank, pj_stream_t stream);
 int pj_list_rank_ex(const int32_t *succ, int64_t n, int32_t *rank, const pj_opts *opts,
@@ -138,7 +142,8 @@ int pj_list_rank_ex(const int32_t *succ, int64_t n, int32_t *rank, const pj_opts
  * [0, size_l) (tail -1 or self).  rank receives local ranks per list.  With
  * opts->h_offsets the host copy is used for planning and no device->host read
  * happens; otherwise offsets[L] is read back (the call then synchronises the
- * stream once).  d_status, when given, holds L entries.
+ * stream once).  d_status, when given, holds L entries.  In place (rank ==
+ * succ) as for pj_list_rank_ex.
  */
 int pj_list_rank_batched(const int32_t *succ, const int64_t *offsets, int64_t L, int32_t *rank,
                          pj_stream_t stream);

@@ -761,9 +761,10 @@ __global__ void __launch_bounds__(1024) wy_final(const unsigned long long* __res
 // ------------------------------------------------------- small one-group
 // A whole batch of at most kMaxCutoff nodes ranked by one workgroup:
 // predecessor links in LDS, pointer jumping along them with unit weights.
-__global__ void __launch_bounds__(kBaseThreads) lr_small(const int32_t* __restrict__ succ,
+// succ is read before any rank is written (in place allowed).
+__global__ void __launch_bounds__(kBaseThreads) lr_small(const int32_t* succ,
                                                          const int64_t* __restrict__ off, int L,
-                                                         int n, int32_t* __restrict__ rank,
+                                                         int n, int32_t* rank,
                                                          int to_tail, int32_t* ltails,
                                                          int32_t* lerr) {
   __shared__ int lnk[kMaxCutoff];
@@ -921,6 +922,19 @@ struct Plan {
   int kbits_far = 0;       // with these offset bits (packed form)
   int max_walk_far = 0;    // and this cut length
 };
+
+// rank may be succ itself (in place: the successors are overwritten by the
+// ranks, the way Section 3.2 reuses the device successor array for the
+// output); any other overlap is rejected.  The full output check reads succ
+// after the ranks are written, so it needs two arrays.
+inline int check_alias(const int32_t* succ, const int32_t* rank, int64_t n, bool validate) {
+  if (n <= 0) return PJ_OK;
+  const uintptr_t s0 = (uintptr_t)succ, r0 = (uintptr_t)rank;
+  const uintptr_t bytes = (uintptr_t)n * sizeof(int32_t);
+  if (s0 == r0) return validate ? PJ_EINVAL : PJ_OK;
+  if (s0 < r0 + bytes && r0 < s0 + bytes) return PJ_EINVAL;
+  return PJ_OK;
+}
 
 inline int bits_for(int64_t v) {  // bits to hold values 0..v-1
   int b = 0;
@@ -1097,7 +1111,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
   }
   if (n0 < 0 || n0 >= INT32_MAX) return PJ_EINVAL;
   if (n0 > 0 && (!succ || !rank)) return PJ_EINVAL;
-  if (n0 > 0 && (const void*)succ == (const void*)rank) return PJ_EINVAL;
+  PJ_TRY(check_alias(succ, rank, n0, o.validate != 0));
   const bool want_status = o.validate && !o.d_status;
   if (n0 == 0 && !o.d_status) return PJ_OK;
 
@@ -1185,14 +1199,16 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     check_tails = true;
     tm.mark("small");
   } else if (n0 > 0) {
-    // level 0 head find (and, in the packed form, the successor copy)
+    // level 0 head find (and, in the packed form, the successor copy, which
+    // in place is already there)
     int32_t* copy = p.packed ? rank : nullptr;
+    const bool copy_succ = p.packed && (const void*)succ != (const void*)rank;
     if (single) {
-      auto k = p.packed ? lr_headfind_single<true> : lr_headfind_single<false>;
+      auto k = copy_succ ? lr_headfind_single<true> : lr_headfind_single<false>;
       hipLaunchKernelGGL(k, dim3(grid_for(n / 4 + 1, 256, 1024)), dim3(256), 0, stream, succ, n,
                          copy, b.lsum, b.ltails, b.lerr, &b.ctl->near);
     } else {
-      auto k = p.packed ? lr_headfind_batched<true> : lr_headfind_batched<false>;
+      auto k = copy_succ ? lr_headfind_batched<true> : lr_headfind_batched<false>;
       hipLaunchKernelGGL(k, dim3(grid_for(n / (kHfChunk * 4) + 1, 256, gcap)), dim3(256), 0,
                          stream, succ, off, Li, n, copy, b.lsum, b.ltails, b.lerr);
     }
@@ -1409,7 +1425,8 @@ int pj_list_rank_batched_ex(const int32_t* succ, const int64_t* offsets, int64_t
     if (ho[0] != 0 || ho[L] < 0 || ho[L] >= INT32_MAX) return PJ_EINVAL;
     for (int64_t l = 0; l < L; ++l)
       if (ho[l + 1] < ho[l]) return PJ_EINVAL;
-    if (ho[L] > 0 && (!succ || !rank || (const void*)succ == (const void*)rank)) return PJ_EINVAL;
+    if (ho[L] > 0 && (!succ || !rank)) return PJ_EINVAL;
+    PJ_TRY(pj::check_alias(succ, rank, ho[L], opts->validate != 0));
     return pj::graph_batched(succ, offsets, L, ho, rank, *opts, (hipStream_t)stream);
   }
   return pj::list_rank_impl(succ, offsets, L, opts ? opts->h_offsets : nullptr, 0, rank, opts,

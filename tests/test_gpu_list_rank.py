@@ -356,3 +356,43 @@ def test_wyllie_reports_rounds(pj, layout):
     torch.cuda.synchronize()
     assert np.array_equal(out.cpu().numpy(), oracle.list_rank(succ))
     assert st["rounds"] == int(np.ceil(np.log2(n)))
+
+
+@pytest.mark.parametrize("case", ["uniform", "sequential", "small", "wyllie", "batched",
+                                  "batched_graph", "to_tail"])
+def test_in_place(pj, case):
+    # rank == succ: the ranks overwrite the successors (Section 3.2)
+    if case.startswith("batched"):
+        succ, off = W.batched_lists(37, 3, 14, 21)
+        want = np.concatenate([oracle.list_rank(succ[off[i]:off[i + 1]]) for i in range(37)])
+        d = dev(succ)
+        kw = dict(use_graph=True) if case == "batched_graph" else {}
+        for _ in range(2 if kw else 1):
+            d.copy_(dev(succ))
+            out = pj.list_rank_batched(d, dev(off), d, h_offsets=off, **kw)
+        torch.cuda.synchronize()
+        assert out.data_ptr() == d.data_ptr()
+        assert np.array_equal(d.cpu().numpy(), want)
+        pj.graph_cache_clear()
+        return
+    n = {"small": 3000, "sequential": 1 << 20}.get(case, 400_009)
+    succ = W.sequential_list(n) if case == "sequential" else W.random_list(n, 23)
+    want = oracle.list_rank(succ)
+    d = dev(succ)
+    kw = {"wyllie": dict(algo="wyllie"), "to_tail": dict(to_tail=True)}.get(case, {})
+    out = pj.list_rank(d, d, **kw)
+    torch.cuda.synchronize()
+    assert out.data_ptr() == d.data_ptr()
+    assert np.array_equal(d.cpu().numpy(), n - 1 - want if case == "to_tail" else want)
+
+
+def test_in_place_rejects_validate_and_partial_overlap(pj):
+    succ = W.random_list(5000, 29)
+    d = dev(succ)
+    with pytest.raises(Exception):
+        pj.list_rank(d, d, validate=True)
+    big = dev(np.concatenate([succ, np.zeros(16, np.int32)]))
+    with pytest.raises(Exception):
+        pj.list_rank(big[:5000], big[8:5008])
+    # the input is untouched by the rejected calls
+    assert np.array_equal(d.cpu().numpy(), succ)
