@@ -337,6 +337,15 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
     ex[f"list_2p{args.log2n}_uniform_wyllie_ms"] = round(ms, 3)
     log(f"wyllie uniform {ms:.3f} ms")
 
+    # weighted ranks on the same list (separate state, weights beside succ)
+    wts = torch.from_numpy(np.random.default_rng(W.SEED_BASE + 7).integers(
+        0, 100, n).astype(np.int32)).to(dev)
+    ms = timed(torch, lambda: pj.list_rank_weighted(d_succ, wts, d_rank), steps, 1)
+    ex[f"list_2p{args.log2n}_uniform_weighted_nodes_per_s"] = round(n / (ms * 1e-3), 1)
+    ex[f"list_2p{args.log2n}_uniform_weighted_ms"] = round(ms, 3)
+    log(f"weighted uniform {ms:.3f} ms")
+    del wts
+
     # other layouts
     for name, s in (("sequential", W.sequential_list(n)),
                     ("blocked", W.blocked_list(n, 4096, W.SEED_BASE + 2))):

@@ -155,6 +155,31 @@ int pj_list_rank_batched_ex(const int32_t *succ, const int64_t *offsets, int64_t
 size_t pj_list_rank_workspace_bytes(int64_t total_nodes, int64_t L, const pj_opts *opts);
 
 /*
+ * Weighted list ranking: the problem the ruling set solves on its splitter
+ * list (Section 3.2, where each splitter carries the length of its sublist).
+ * weight is a DEVICE int32[n] array beside succ; rank[i] receives the sum of
+ * the weights of the nodes before i in its list (exclusive prefix from the
+ * head: rank[head] = 0, rank[succ[i]] = rank[i] + weight[i]).  Unit weights
+ * give pj_list_rank's result.  Sums are int32: the total weight of a list
+ * must fit, or the ranks are unspecified.  Always the ruling-set method;
+ * opts->algo == PJ_ALGO_WYLLIE, opts->to_tail and opts->validate are
+ * PJ_EINVAL (d_status still reports malformed lists), opts->use_graph is
+ * ignored.  rank may be succ itself (in place); rank must not overlap
+ * weight.  weight may be null only when there is nothing to rank.
+ */
+int pj_list_rank_weighted(const int32_t *succ, const int32_t *weight, int64_t n, int32_t *rank,
+                          const pj_opts *opts, pj_stream_t stream);
+/* The batched form (offsets and local ids as for pj_list_rank_batched_ex;
+ * weight is laid out like succ). */
+int pj_list_rank_weighted_batched(const int32_t *succ, const int32_t *weight,
+                                  const int64_t *offsets, int64_t L, int32_t *rank,
+                                  const pj_opts *opts, pj_stream_t stream);
+/* Workspace bytes of the weighted calls (their level-0 state is not packed
+ * into the output, so they need 8 more bytes per node). */
+size_t pj_list_rank_weighted_workspace_bytes(int64_t total_nodes, int64_t L,
+                                             const pj_opts *opts);
+
+/*
  * Batched list ranking with opts->use_graph = 1 captures the call's whole
  * launch sequence once into a hipGraph (keyed by the buffers, sizes and
  * options; the cache owns the workspace) and replays it with one

@@ -10,6 +10,8 @@ The arithmetic lives in `oracle.c` (plain sequential C, built with gcc by
   list_rank(succ)          distance from the head, per the list-ranking
                            problem statement (Section 3); tail marked -1 or
                            by a self-loop.
+  list_rank_weighted(..)   sum of the weights of the nodes before each node
+                           (the weighted splitter list of Section 3.2).
   connected_components(..) smallest vertex id of each component, per the
                            connected-components problem statement (Section 4).
   *_batched                the same per instance of an offset-table batch.
@@ -50,6 +52,8 @@ def _load():
     i64p = ctypes.POINTER(ctypes.c_int64)
     lib.oracle_list_rank.argtypes = [i32p, ctypes.c_int64, i32p]
     lib.oracle_list_rank.restype = ctypes.c_int
+    lib.oracle_list_rank_weighted.argtypes = [i32p, i32p, ctypes.c_int64, i32p]
+    lib.oracle_list_rank_weighted.restype = ctypes.c_int
     lib.oracle_cc.argtypes = [i32p, i32p, ctypes.c_int64, ctypes.c_int64, i32p]
     lib.oracle_cc.restype = ctypes.c_int
     lib.oracle_list_rank_batched.argtypes = [i32p, i64p, ctypes.c_int64, i32p, i32p, ctypes.c_int]
@@ -83,6 +87,18 @@ def list_rank_status(succ):
 
 def list_rank(succ):
     rc, rank = list_rank_status(succ)
+    if rc != OK:
+        raise OracleError(rc)
+    return rank
+
+
+def list_rank_weighted(succ, weight):
+    """rank[x] = sum of the weights of the nodes before x (int32, wrapping)."""
+    succ, weight = _i32(succ), _i32(weight)
+    if succ.shape != weight.shape:
+        raise ValueError("succ and weight differ in length")
+    rank = np.full(succ.shape[0], -1, dtype=np.int32)
+    rc = _load().oracle_list_rank_weighted(_p32(succ), _p32(weight), succ.shape[0], _p32(rank))
     if rc != OK:
         raise OracleError(rc)
     return rank

@@ -14,6 +14,12 @@
  *     (rank[head] = 0, rank[succ[i]] = rank[i] + 1); the paper's "distance to
  *     the last element" is n - 1 minus this value.
  *
+ *   weighted list ranking (the splitter list of Section 3.2, whose nodes
+ *     carry their sublist lengths as weights): rank[x] = the sum of the weights
+ *     of the nodes before x in list order (exclusive prefix from the head),
+ *     in 32-bit two's complement (sums wrap modulo 2^32).  Unit weights give
+ *     the unweighted rank.
+ *
  *   connected components (Section 4, problem statement): an undirected graph
  *     given by m vertex pairs; label[v] is the smallest vertex id in v's
  *     component.  Computed with a sequential union-find (union by size, path
@@ -39,8 +45,9 @@
 
 /* ---------------------------------------------------------------- lists -- */
 
-/* Distance from the head for one list of n nodes (local ids 0..n-1). */
-int oracle_list_rank(const int32_t *succ, int64_t n, int32_t *rank)
+/* Rank from the head for one list of n nodes (local ids 0..n-1): the number
+ * of nodes before each node, or with weights the sum of their weights. */
+static int rank_one(const int32_t *succ, const int32_t *weight, int64_t n, int32_t *rank)
 {
     if (n < 0 || n > INT32_MAX) return OR_EINVAL;
     if (n == 0) return OR_OK;
@@ -69,13 +76,17 @@ int oracle_list_rank(const int32_t *succ, int64_t n, int32_t *rank)
         if (!mark[i]) { ++heads; head = i; }
     if (heads != 1) { free(mark); return OR_EBADLIST; }
 
-    /* 3. walk from the head, numbering the nodes 0, 1, 2, ... */
+    /* 3. walk from the head: each node gets the count (or weight sum) of the
+     *    nodes walked before it */
     memset(mark, 0, (size_t)n);
     int64_t r = 0, cur = head;
+    uint32_t acc = 0;
     for (;;) {
         if (mark[cur]) { free(mark); return OR_EBADLIST; }
         mark[cur] = 1;
-        rank[cur] = (int32_t)r++;
+        ++r;
+        rank[cur] = (int32_t)acc;
+        acc += weight ? (uint32_t)weight[cur] : 1u;
         int32_t nx = succ[cur];
         if (nx == -1 || nx == (int32_t)cur) break;
         cur = nx;
@@ -84,6 +95,18 @@ int oracle_list_rank(const int32_t *succ, int64_t n, int32_t *rank)
 
     /* 4. the walk covered every node (otherwise a detached cycle exists) */
     return r == n ? OR_OK : OR_EBADLIST;
+}
+
+int oracle_list_rank(const int32_t *succ, int64_t n, int32_t *rank)
+{
+    return rank_one(succ, NULL, n, rank);
+}
+
+int oracle_list_rank_weighted(const int32_t *succ, const int32_t *weight, int64_t n,
+                              int32_t *rank)
+{
+    if (n > 0 && !weight) return OR_EINVAL;
+    return rank_one(succ, weight, n, rank);
 }
 
 /* ------------------------------------------------------------ components -- */

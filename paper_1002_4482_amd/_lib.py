@@ -137,6 +137,9 @@ SIGNATURES = [
     ("pj_list_rank_batched", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP]),
     ("pj_list_rank_batched_ex", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _VP]),
     ("pj_list_rank_workspace_bytes", _SZ, [_I64, _I64, _VP]),
+    ("pj_list_rank_weighted", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _VP]),
+    ("pj_list_rank_weighted_batched", ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP, _VP]),
+    ("pj_list_rank_weighted_workspace_bytes", _SZ, [_I64, _I64, _VP]),
     ("pj_connected_components", ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, _VP]),
     ("pj_connected_components_ex", ctypes.c_int, [_VP, _VP, _I64, _I64, _VP, _VP, _VP]),
     ("pj_connected_components_batched", ctypes.c_int, [_VP, _VP, _VP, _VP, _I64, _VP, _VP]),

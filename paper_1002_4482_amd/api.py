@@ -130,6 +130,50 @@ def list_rank_batched(succ, offsets, rank=None, *, h_offsets=None, stream=None,
     return (rank, st.to_dict()) if return_stats else rank
 
 
+def list_rank_weighted(succ, weight, rank=None, *, stream=None, return_stats=False, **kw):
+    """Weighted ranks of one list: rank[i] = sum of the weights of the nodes
+    before i (int32 on the device, `weight` beside `succ`)."""
+    succ = _dev_i32(succ, "succ")
+    weight = _dev_i32(weight, "weight")
+    n = succ.numel()
+    _need(weight, n, "weight")
+    if rank is None:
+        rank = torch.empty_like(succ)
+    _dev_i32(rank, "rank")
+    _need(rank, n, "rank")
+    st = PjStats() if return_stats else None
+    o = make_opts(stats=st, **kw)
+    rc = _lib.load().pj_list_rank_weighted(_ptr(succ), _ptr(weight), n, _ptr(rank),
+                                           ctypes.byref(o), _stream_ptr(stream))
+    _check(rc, "pj_list_rank_weighted")
+    return (rank, st.to_dict()) if return_stats else rank
+
+
+def list_rank_weighted_batched(succ, weight, offsets, rank=None, *, h_offsets=None, stream=None,
+                               return_stats=False, **kw):
+    """Weighted ranks of L concatenated lists (local ids, device int64
+    offsets[L+1], `weight` laid out like `succ`)."""
+    succ = _dev_i32(succ, "succ")
+    weight = _dev_i32(weight, "weight")
+    _need(weight, succ.numel(), "weight")
+    offsets = _dev_i64(offsets, "offsets")
+    L = offsets.numel() - 1
+    if rank is None:
+        rank = torch.empty_like(succ)
+    _dev_i32(rank, "rank")
+    _need(rank, succ.numel(), "rank")
+    h_offsets = _host_i64(h_offsets, L + 1, "h_offsets")
+    if h_offsets is not None and h_offsets[-1] > succ.numel():
+        raise ValueError("offsets exceed succ")
+    st = PjStats() if return_stats else None
+    o = make_opts(stats=st, h_offsets=h_offsets, **kw)
+    rc = _lib.load().pj_list_rank_weighted_batched(_ptr(succ), _ptr(weight), _ptr(offsets), L,
+                                                   _ptr(rank), ctypes.byref(o),
+                                                   _stream_ptr(stream))
+    _check(rc, "pj_list_rank_weighted_batched")
+    return (rank, st.to_dict()) if return_stats else rank
+
+
 def connected_components(src, dst, n, label=None, *, stream=None, return_stats=False, **kw):
     """label[v] = smallest vertex id in v's component (device int32 pairs)."""
     src = _dev_i32(src, "src")

@@ -232,6 +232,7 @@ __global__ void __launch_bounds__(256) lr_headfind_batched(const int32_t* __rest
 // ------------------------------------------------------------------ walk
 struct WalkArgs {
   const int32_t* succ0;              // level 0: local successors
+  const int32_t* weight0;            // level 0, weighted call: node weights (unpacked form)
   const int2* link_in;               // level >= 1: {next, weight} per node
   const int64_t* off;                // level 0: list offsets (L+1)
   const unsigned long long* lsum;    // level 0: head-find sums
@@ -390,7 +391,7 @@ __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
           tail = true;
         }
         y = (int)(base + s);
-        w = 1;
+        w = (!kPacked && a.weight0) ? a.weight0[x] : 1;
       } else {
         const int2 in = a.link_in[x];
         tail = in.x == -1;
@@ -761,8 +762,10 @@ __global__ void __launch_bounds__(1024) wy_final(const unsigned long long* __res
 // ------------------------------------------------------- small one-group
 // A whole batch of at most kMaxCutoff nodes ranked by one workgroup:
 // predecessor links in LDS, pointer jumping along them with unit weights.
-// succ is read before any rank is written (in place allowed).
+// succ is read before any rank is written (in place allowed).  With weights,
+// a node's own term is its predecessor's weight instead of 1.
 __global__ void __launch_bounds__(kBaseThreads) lr_small(const int32_t* succ,
+                                                         const int32_t* weight,
                                                          const int64_t* __restrict__ off, int L,
                                                          int n, int32_t* rank,
                                                          int to_tail, int32_t* ltails,
@@ -787,7 +790,10 @@ __global__ void __launch_bounds__(kBaseThreads) lr_small(const int32_t* succ,
     }
   }
   __syncthreads();
-  for (int j = tid; j < n; j += kBaseThreads) pre[j] = lnk[j] >= 0 ? 1 : 0;
+  for (int j = tid; j < n; j += kBaseThreads) {
+    const int p = lnk[j];
+    pre[j] = p >= 0 ? (weight ? weight[p] : 1) : 0;
+  }
   __syncthreads();
   int rounds = 0;
   while ((1 << rounds) < n) ++rounds;
@@ -942,7 +948,9 @@ inline int bits_for(int64_t v) {  // bits to hold values 0..v-1
   return b;
 }
 
-Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o) {
+// pack = false keeps level 0 in the separate (sublist, offset) state, which
+// weighted calls need (an offset is then a weight sum, not a step count).
+Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o, bool pack = true) {
   Plan p;
   p.algo = o.algo == PJ_ALGO_WYLLIE ? PJ_ALGO_WYLLIE : PJ_ALGO_RULING_SET;
   p.bound[0] = n0;
@@ -976,7 +984,7 @@ Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o) {
       // Pack (sublist id, offset) into 31 bits when the id space allows an
       // offset of at least 4 bits; the cut length then bounds the offset.
       p.packed = false;
-      for (int kb = bits_for(mw); kb >= 4; --kb) {
+      for (int kb = bits_for(mw); pack && kb >= 4; --kb) {
         const int mwk = std::min(mw, 1 << kb);
         const int64_t ids = r + L + b / mwk + 64;
         if (bits_for(ids) + kb <= 31) {
@@ -1073,7 +1081,8 @@ size_t carve(const Plan& p, int64_t L, bool single, bool validate, bool want_sta
 }  // namespace
 
 int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,
-                   int64_t n_single, int32_t* rank, const pj_opts* user, hipStream_t stream) {
+                   int64_t n_single, int32_t* rank, const pj_opts* user, hipStream_t stream,
+                   const int32_t* weight) {
   const bool single = d_off == nullptr;
   if (L < 0) return PJ_EINVAL;
   if (single) L = 1;
@@ -1112,6 +1121,15 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
   if (n0 < 0 || n0 >= INT32_MAX) return PJ_EINVAL;
   if (n0 > 0 && (!succ || !rank)) return PJ_EINVAL;
   PJ_TRY(check_alias(succ, rank, n0, o.validate != 0));
+  if (weight) {
+    // weighted ranks are exclusive prefix sums from the head by the ruling
+    // set; the to-tail form and the full check (a permutation test) do not
+    // apply
+    if (o.algo == PJ_ALGO_WYLLIE || o.to_tail || o.validate) return PJ_EINVAL;
+    const uintptr_t w0 = (uintptr_t)weight, r0 = (uintptr_t)rank;
+    const uintptr_t bytes = (uintptr_t)n0 * sizeof(int32_t);
+    if (n0 > 0 && w0 < r0 + bytes && r0 < w0 + bytes) return PJ_EINVAL;
+  }
   const bool want_status = o.validate && !o.d_status;
   if (n0 == 0 && !o.d_status) return PJ_OK;
 
@@ -1127,7 +1145,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     o.max_walk = raw.max_walk > 0 ? std::max(raw.max_walk, 16) : o.max_walk;
     if (raw.block > 0) o.block = std::min(1024, (raw.block + 63) / 64 * 64);
   }
-  Plan p = make_plan(n0, L, max_size, o);
+  Plan p = make_plan(n0, L, max_size, o, weight == nullptr);
   add_far_spacing(p, n0, L, far_spacing, o.max_walk);
   Buffers b;
   const size_t need = carve(p, L, single, o.validate != 0, want_status, nullptr, &b);
@@ -1194,8 +1212,8 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     }
     tm.mark("wyllie_final");
   } else if (n0 > 0 && p.small) {
-    hipLaunchKernelGGL(lr_small, dim3(1), dim3(kBaseThreads), 0, stream, succ, off, Li, n, rank,
-                       o.to_tail, b.ltails, b.lerr);
+    hipLaunchKernelGGL(lr_small, dim3(1), dim3(kBaseThreads), 0, stream, succ, weight, off, Li,
+                       n, rank, o.to_tail, b.ltails, b.lerr);
     check_tails = true;
     tm.mark("small");
   } else if (n0 > 0) {
@@ -1220,6 +1238,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     for (int lv = 0; lv < p.levels; ++lv) {
       WalkArgs a{};
       a.succ0 = succ;
+      a.weight0 = weight;
       a.link_in = b.link[lv];
       a.off = off;
       a.lsum = b.lsum;
@@ -1383,14 +1402,15 @@ int level0_spacing(int requested, int64_t n0, bool single, int32_t* planned) {
   return 0;
 }
 
-size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single) {
+size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single,
+                           bool weighted) {
   pj_opts raw;
   pj_opts_init(&raw);
   if (user) raw = *user;
   apply_tuned(raw, n0, L);
   (void)level0_spacing(raw.spacing, n0, single, &raw.spacing);
   pj_opts o = resolved_opts(&raw);
-  Plan p = make_plan(n0, L, n0, o);
+  Plan p = make_plan(n0, L, n0, o, !weighted);
   Buffers b;
   return carve(p, L, single, o.validate != 0, o.validate && !o.d_status, nullptr, &b);
 }
@@ -1436,6 +1456,29 @@ int pj_list_rank_batched_ex(const int32_t* succ, const int64_t* offsets, int64_t
 int pj_list_rank_batched(const int32_t* succ, const int64_t* offsets, int64_t L, int32_t* rank,
                          pj_stream_t stream) {
   return pj_list_rank_batched_ex(succ, offsets, L, rank, nullptr, stream);
+}
+
+int pj_list_rank_weighted(const int32_t* succ, const int32_t* weight, int64_t n, int32_t* rank,
+                          const pj_opts* opts, pj_stream_t stream) {
+  if (n < 0 || (n > 0 && !weight)) return PJ_EINVAL;
+  return pj::list_rank_impl(succ, nullptr, 1, nullptr, n, rank, opts, (hipStream_t)stream,
+                            n > 0 ? weight : nullptr);
+}
+
+int pj_list_rank_weighted_batched(const int32_t* succ, const int32_t* weight,
+                                  const int64_t* offsets, int64_t L, int32_t* rank,
+                                  const pj_opts* opts, pj_stream_t stream) {
+  if (!offsets || L < 0 || (L > 0 && !weight)) return PJ_EINVAL;
+  return pj::list_rank_impl(succ, offsets, L, opts ? opts->h_offsets : nullptr, 0, rank, opts,
+                            (hipStream_t)stream, weight);
+}
+
+size_t pj_list_rank_weighted_workspace_bytes(int64_t total_nodes, int64_t L,
+                                             const pj_opts* opts) {
+  if (total_nodes < 0 || L < 1) return 0;
+  const size_t batched = pj::list_rank_workspace(total_nodes, L, opts, false, true);
+  return L > 1 ? batched
+               : std::max(batched, pj::list_rank_workspace(total_nodes, L, opts, true, true));
 }
 
 size_t pj_list_rank_workspace_bytes(int64_t total_nodes, int64_t L, const pj_opts* opts) {

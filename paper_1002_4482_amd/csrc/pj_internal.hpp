@@ -131,9 +131,12 @@ pj_opts resolved_opts(const pj_opts* in);
 
 // List ranking entry shared by the plain, batched, graph and tuning paths.
 // d_off == nullptr means one list of n_single nodes.
+// weight != nullptr: weighted ranks (exclusive prefix sums of the weights).
 int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,
-                   int64_t n_single, int32_t* rank, const pj_opts* user, hipStream_t stream);
-size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single);
+                   int64_t n_single, int32_t* rank, const pj_opts* user, hipStream_t stream,
+                   const int32_t* weight = nullptr);
+size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single,
+                           bool weighted = false);
 int list_rank_default_spacing(int64_t n);
 int level0_spacing(int requested, int64_t n0, bool single, int32_t* planned);
 

@@ -396,3 +396,97 @@ def test_in_place_rejects_validate_and_partial_overlap(pj):
         pj.list_rank(big[:5000], big[8:5008])
     # the input is untouched by the rejected calls
     assert np.array_equal(d.cpu().numpy(), succ)
+
+
+# ------------------------------------------------------------ weighted lists
+
+def _weights(n, seed, lo=-1000, hi=1000):
+    return np.random.default_rng(seed).integers(lo, hi, n).astype(np.int32)
+
+
+@pytest.mark.parametrize("n", SIZES)
+def test_weighted_matches_oracle(pj, n):
+    succ = W.random_list(n, 31 + n % 7)
+    w = _weights(n, n)
+    got = pj.list_rank_weighted(dev(succ), dev(w))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.list_rank_weighted(succ, w))
+
+
+@pytest.mark.parametrize("params", [
+    dict(), dict(spacing=2), dict(spacing=64, spacing_up=16), dict(max_walk=16),
+    dict(cutoff=64), dict(block=1024, spacing=128), dict(seed=99),
+])
+@pytest.mark.parametrize("layout", ["uniform", "sequential", "blocked"])
+def test_weighted_layouts_and_parameters(pj, params, layout):
+    n = 300_007
+    if layout == "uniform":
+        succ = W.random_list(n, 41)
+    elif layout == "sequential":
+        succ = W.sequential_list(n)
+    else:
+        succ = W.blocked_list(n, 4096, 42)
+    w = _weights(n, 43, 0, 50)
+    got = pj.list_rank_weighted(dev(succ), dev(w), **params)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.list_rank_weighted(succ, w))
+
+
+def test_weighted_unit_weights_and_in_place(pj):
+    n = 1 << 20
+    succ = W.random_list(n, 47)
+    want = oracle.list_rank(succ)
+    got = pj.list_rank_weighted(dev(succ), dev(np.ones(n, np.int32)))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    w = _weights(n, 48)
+    d = dev(succ)
+    out = pj.list_rank_weighted(d, dev(w), d)
+    torch.cuda.synchronize()
+    assert out.data_ptr() == d.data_ptr()
+    assert np.array_equal(d.cpu().numpy(), oracle.list_rank_weighted(succ, w))
+
+
+def test_weighted_closed_form_large(pj):
+    # rank[order[k]] = exclusive prefix of the weights along the list order
+    n = 1 << 24
+    succ, order = W.random_list_with_order(n, 49)
+    w = _weights(n, 50, 0, 100)
+    got = pj.list_rank_weighted(dev(succ), dev(w))
+    do = torch.from_numpy(order.astype(np.int64)).cuda()
+    wo = dev(w)[do].to(torch.int64)
+    want = torch.cumsum(wo, 0) - wo
+    assert torch.equal(got[do].to(torch.int64), want)
+
+
+@pytest.mark.parametrize("L,lo,hi", [(37, 3, 14), (500, 1, 10), (3, 16, 19)])
+def test_weighted_batched(pj, L, lo, hi):
+    succ, off = W.batched_lists(L, lo, hi, 51 + L)
+    w = _weights(succ.shape[0], 52 + L)
+    want = np.concatenate([oracle.list_rank_weighted(succ[off[i]:off[i + 1]],
+                                                     w[off[i]:off[i + 1]]) for i in range(L)])
+    got = pj.list_rank_weighted_batched(dev(succ), dev(w), dev(off), h_offsets=off)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    got2 = pj.list_rank_weighted_batched(dev(succ), dev(w), dev(off))
+    torch.cuda.synchronize()
+    assert np.array_equal(got2.cpu().numpy(), want)
+
+
+def test_weighted_rejects_and_reports(pj):
+    n = 5000
+    succ = W.random_list(n, 53)
+    w = _weights(n, 54)
+    for kw in (dict(algo="wyllie"), dict(to_tail=True), dict(validate=True)):
+        with pytest.raises(Exception):
+            pj.list_rank_weighted(dev(succ), dev(w), **kw)
+    dw = dev(w)
+    with pytest.raises(Exception):
+        pj.list_rank_weighted(dev(succ), dw, dw)
+    # malformed list: the status names it
+    bad = succ.copy()
+    bad[int(np.nonzero(bad != -1)[0][0])] = -1  # a second tail: two lists
+    st = torch.empty(1, dtype=torch.int32, device="cuda")
+    pj.list_rank_weighted(dev(bad), dev(w), status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == pj.PJ_EBADLIST

@@ -144,3 +144,52 @@ def test_pins_catch_planted_mistakes(mistake):
     assert mistake(succ).tolist() != g["rank_from_head"]
     with pytest.raises(AssertionError):
         check_rank_invariants(succ, mistake(succ))
+
+
+# ------------------------------------------------------------ weighted lists
+# The weighted form ranks the splitter list of Section 3.2 (sublist lengths as
+# weights): rank[x] = sum of the weights of the nodes before x.
+
+def _weighted_brute(order, weight):
+    """Exclusive prefix of the weights along `order`, by explicit summation."""
+    rank = [0] * len(order)
+    for k, v in enumerate(order):
+        rank[v] = sum(int(weight[u]) for u in order[:k])
+    return rank
+
+
+@pytest.mark.parametrize("n", range(1, 7))
+def test_weighted_every_permutation_brute_force(n):
+    rng = np.random.default_rng(n)
+    for order in itertools.permutations(range(n)):
+        succ = [-1] * n
+        for a, b in zip(order, order[1:]):
+            succ[a] = b
+        w = rng.integers(-9, 10, n).astype(np.int32)
+        got = oracle.list_rank_weighted(np.array(succ, dtype=np.int32), w).tolist()
+        assert got == _weighted_brute(order, w)
+
+
+@pytest.mark.parametrize("n,seed", [(1, 1), (2, 2), (1000, 3), (100_003, 4)])
+def test_weighted_closed_form_and_unit_weights(n, seed):
+    succ, order = W.random_list_with_order(n, seed)
+    w = np.random.default_rng(seed).integers(-1000, 1000, n).astype(np.int32)
+    want = np.empty(n, dtype=np.int64)
+    want[order] = np.concatenate([[0], np.cumsum(w[order].astype(np.int64))[:-1]])
+    assert np.array_equal(oracle.list_rank_weighted(succ, w), want.astype(np.int32))
+    assert np.array_equal(oracle.list_rank_weighted(succ, np.ones(n, np.int32)),
+                          oracle.list_rank(succ))
+    # self-loop tail marker: same ranks
+    assert np.array_equal(oracle.list_rank_weighted(W.to_self_loop_tails(succ), w),
+                          want.astype(np.int32))
+
+
+def test_weighted_wraps_and_rejects():
+    big = np.int32(2**31 - 1)
+    succ = np.array([1, 2, -1], dtype=np.int32)
+    # sums wrap modulo 2^32: 2 * (2^31 - 1) = 2^32 - 2 -> -2
+    assert oracle.list_rank_weighted(succ, np.array([big, big, 5], np.int32)).tolist() == [0, big, -2]
+    with pytest.raises(ValueError):
+        oracle.list_rank_weighted(succ, np.ones(2, np.int32))
+    with pytest.raises(oracle.OracleError):
+        oracle.list_rank_weighted(np.array([1, 0, -1], np.int32), np.ones(3, np.int32))
