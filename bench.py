@@ -216,6 +216,20 @@ def main():
         cpu = {"value": round(n / dt, 1), "unit": "nodes/s", "cores": 1, "kind": "oracle",
                "sample": f"one sequential walk over the whole 2^{args.log2n}-node uniform list "
                          f"with validation ({dt:.2f} s)"}
+        # the paper's multi-core comparison: random splitters on POSIX threads
+        threads = min(16, os.cpu_count() or 1)
+        best = None
+        for _ in range(3):
+            t = time.perf_counter()
+            rc, mt = oracle.cpu_ruling_set(succ, 64, threads)
+            dt = time.perf_counter() - t
+            best = dt if best is None else min(best, dt)
+        assert rc == 0 and np.array_equal(mt, ref)
+        extras["cpu_ruling_set_threads"] = {
+            "value": round(n / best, 1), "unit": "nodes/s", "cores": threads,
+            "ms": round(best * 1e3, 1),
+            "sample": f"the same list, spacing 64, best of 3 runs"}
+        log(f"CPU ruling set on {threads} threads: {best * 1e3:.1f} ms")
 
     out = {
         "metric": METRIC,

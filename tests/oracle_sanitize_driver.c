@@ -3,7 +3,8 @@
  * UndefinedBehaviorSanitizer (built by tests/test_oracle_sanitize.py with gcc,
  * host code only).  Valid and malformed lists, graphs with self-loops,
  * duplicates and isolated vertices, and both batched forms on several
- * threads.  Exits non-zero on a wrong result; the sanitizers abort on a
+ * threads; the weighted ranking and the multi-threaded CPU baseline on the
+ * same lists.  Exits non-zero on a wrong result; the sanitizers abort on a
  * memory or UB error.
  */
 #include <stdint.h>
@@ -11,6 +12,10 @@
 #include <stdlib.h>
 
 int oracle_list_rank(const int32_t *succ, int64_t n, int32_t *rank);
+int oracle_list_rank_weighted(const int32_t *succ, const int32_t *weight, int64_t n,
+                              int32_t *rank);
+int cpu_ruling_set_list_rank(const int32_t *succ, int64_t n, int32_t *rank, int spacing,
+                             int nthreads);
 int oracle_cc(const int32_t *src, const int32_t *dst, int64_t n, int64_t m, int32_t *label);
 int oracle_list_rank_batched(const int32_t *succ, const int64_t *off, int64_t L, int32_t *rank,
                              int32_t *status, int nthreads);
@@ -39,17 +44,31 @@ static int check_list(int32_t n) {
     random_order(order, n);
     for (int32_t k = 0; k + 1 < n; ++k) succ[order[k]] = order[k + 1];
     if (n) succ[order[n - 1]] = (n & 1) ? -1 : order[n - 1];
+    int32_t *weight = malloc(sizeof(int32_t) * (n ? n : 1));
     int bad = oracle_list_rank(succ, n, rank) != 0;
+    for (int32_t k = 0; k < n && !bad; ++k) bad = rank[order[k]] != k;
+    /* weighted: the exclusive prefix of the weights along the order */
+    for (int32_t i = 0; i < n; ++i) weight[i] = (int32_t)(next_u32() % 2001) - 1000;
+    bad |= oracle_list_rank_weighted(succ, weight, n, rank) != 0;
+    int64_t acc = 0;
+    for (int32_t k = 0; k < n && !bad; ++k) {
+        bad = rank[order[k]] != (int32_t)acc;
+        acc += weight[order[k]];
+    }
+    /* the CPU baseline on 3 threads, one splitter per ~4 nodes */
+    bad |= cpu_ruling_set_list_rank(succ, n, rank, 4, 3) != 0;
     for (int32_t k = 0; k < n && !bad; ++k) bad = rank[order[k]] != k;
     if (n > 2) {  /* a second tail, then a cycle: both rejected */
         int32_t keep = succ[order[n / 2]];
         succ[order[n / 2]] = -1;
         bad |= oracle_list_rank(succ, n, rank) != -4;
+        bad |= cpu_ruling_set_list_rank(succ, n, rank, 4, 3) != -4;
         succ[order[n / 2]] = keep;
         succ[order[n - 1]] = order[0];
         bad |= oracle_list_rank(succ, n, rank) != -4;
+        bad |= cpu_ruling_set_list_rank(succ, n, rank, 4, 3) != -4;
     }
-    free(order); free(succ); free(rank);
+    free(order); free(succ); free(rank); free(weight);
     return bad;
 }
 
