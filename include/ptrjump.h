@@ -75,8 +75,9 @@ typedef struct pj_opts {
                                  kernels, multiple of 64 in [64, 1024] (zero: 256) */
     int32_t spacing;          /* ruling set, first level: one splitter per `spacing`
                                  consecutive node ids (power of two, 2..65536);
-                                 zero: 8, 16, 32 or 64 as n grows past 2^23,
-                                 2^24, 2^25 (a single list of >= 2^24 nodes
+                                 zero: n / 2^20 rounded down to a power of
+                                 two, within 8..256 for one list and 8..64
+                                 for a batch (a single list of >= 2^24 nodes
                                  keeps 8 when most successors are local) */
     int32_t spacing_up;       /* ruling set, recursion levels: same meaning
                                  (zero: 4) */
@@ -192,7 +193,7 @@ void pj_graph_cache_clear(void);
 /* ------------------------------------------------------------- autotuner */
 /*
  * Times ruling-set parameters on this input by coordinate descent from the
- * defaults (first-level spacing 8..128, recursion spacing 4..16, LDS cutoff
+ * defaults (first-level spacing 8..256, recursion spacing 4..16, LDS cutoff
  * 2048..16384, workgroup size of the sublist walks 128..1024, each swept with
  * the others at their best so far) and records the fastest in the tune
  * cache, keyed by (gfx arch, ceil(log2 nodes), ceil(log2 lists)).  Later

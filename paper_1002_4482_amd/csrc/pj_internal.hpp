@@ -137,7 +137,7 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
                    const int32_t* weight = nullptr);
 size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool single,
                            bool weighted = false);
-int list_rank_default_spacing(int64_t n);
+int list_rank_default_spacing(int64_t n, bool single);
 int level0_spacing(int requested, int64_t n0, bool single, int32_t* planned);
 
 // Tuned ruling-set parameters for a problem of n0 nodes in L lists, if the
