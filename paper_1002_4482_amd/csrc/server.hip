@@ -56,6 +56,8 @@ size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
 
 }  // namespace
 
+struct HostStage;
+
 struct Server {
   // configuration
   size_t budget = 0;
@@ -116,7 +118,7 @@ struct Server {
 
   void scheduler_loop();
   void worker_loop(int idx);
-  int run_tick(Tick* t, hipStream_t s);
+  int run_tick(Tick* t, hipStream_t s, HostStage& stage);
   void finish_tick(Tick* t, bool ok);
 };
 
@@ -157,11 +159,41 @@ void Server::scheduler_loop() {
   }
 }
 
+// A worker's pinned host staging for tick tables and statuses, kept across
+// ticks (pinning memory per tick costs more than a small tick's solve).  A
+// tick ends with a stream synchronisation, so the next tick may reuse it.
+struct HostStage {
+  char* p = nullptr;
+  size_t cap = 0;
+  HostStage() = default;
+  HostStage(const HostStage&) = delete;
+  HostStage& operator=(const HostStage&) = delete;
+  ~HostStage() {
+    if (p) (void)hipHostFree(p);
+  }
+  char* get(size_t bytes) {
+    if (bytes > cap) {
+      if (p) (void)hipHostFree(p);
+      p = nullptr;
+      cap = 0;
+      size_t c = 64 << 10;
+      while (c < bytes) c *= 2;
+      if (hipHostMalloc((void**)&p, c, hipHostMallocDefault) != hipSuccess) {
+        p = nullptr;
+        return nullptr;
+      }
+      cap = c;
+    }
+    return p;
+  }
+};
+
 void Server::worker_loop(int idx) {
   (void)idx;
   (void)hipSetDevice(device);
   hipStream_t s = nullptr;
   if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) s = nullptr;
+  HostStage stage;
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
     cv_work.wait(lk, [&] { return !ready.empty() || (stopping && pending.empty()); });
@@ -175,7 +207,7 @@ void Server::worker_loop(int idx) {
     ++busy_workers;
     inflight_peak = std::max(inflight_peak, busy_workers);
     lk.unlock();
-    const int rc = s ? run_tick(t, s) : PJ_EHIP;
+    const int rc = s ? run_tick(t, s, stage) : PJ_EHIP;
     lk.lock();
     finish_tick(t, rc == PJ_OK);
     --busy_workers;
@@ -205,7 +237,7 @@ void Server::finish_tick(Tick* t, bool ok) {
   }
 }
 
-int Server::run_tick(Tick* t, hipStream_t s) {
+int Server::run_tick(Tick* t, hipStream_t s, HostStage& stage) {
   std::vector<Request*> lr, cc;
   for (auto* r : t->reqs) (r->kind == 0 ? lr : cc).push_back(r);
   const int64_t L = (int64_t)lr.size(), G = (int64_t)cc.size();
@@ -217,8 +249,8 @@ int Server::run_tick(Tick* t, hipStream_t s) {
   }
   // host staging for tables and statuses (pinned so copies stay asynchronous)
   const size_t hbytes = (L + 1 + 2 * (G + 1)) * 8 + (L + G) * 4 + 64;
-  char* hst = nullptr;
-  PJ_HIP(hipHostMalloc((void**)&hst, hbytes, hipHostMallocDefault));
+  char* hst = stage.get(hbytes);
+  if (!hst) return PJ_ENOMEM;
   int64_t* h_loff = reinterpret_cast<int64_t*>(hst);
   int64_t* h_voff = h_loff + (L + 1);
   int64_t* h_eoff = h_voff + (G + 1);
@@ -232,7 +264,6 @@ int Server::run_tick(Tick* t, hipStream_t s) {
   int rc = PJ_OK;
   hipError_t he = hipMallocAsync((void**)&d, std::max<size_t>(t->bytes, 256), s);
   if (he != hipSuccess) {
-    (void)hipHostFree(hst);
     set_last_hip_error(he, "hipMallocAsync(tick)", __FILE__, __LINE__);
     return PJ_ENOMEM;
   }
@@ -350,7 +381,6 @@ int Server::run_tick(Tick* t, hipStream_t s) {
   (void)hipStreamSynchronize(s);
   for (int64_t i = 0; i < L; ++i) lr[i]->status = rc == PJ_OK ? h_lst[i] : rc;
   for (int64_t i = 0; i < G; ++i) cc[i]->status = rc == PJ_OK ? h_cst[i] : rc;
-  (void)hipHostFree(hst);
   return PJ_OK;
 }
 
