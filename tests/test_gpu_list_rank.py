@@ -490,3 +490,31 @@ def test_weighted_rejects_and_reports(pj):
     pj.list_rank_weighted(dev(bad), dev(w), status=st)
     torch.cuda.synchronize()
     assert int(st.item()) == pj.PJ_EBADLIST
+
+
+def test_weighted_edge_cases(pj):
+    # n = 1 and 2, all-zero weights, a batch with empty and one-node lists,
+    # and cut points (max_walk 16) with large weights near the int32 range
+    for succ, w in (([-1], [7]), ([1, -1], [3, 4]), ([-1, 0], [3, 4])):
+        succ, w = np.array(succ, np.int32), np.array(w, np.int32)
+        got = pj.list_rank_weighted(dev(succ), dev(w))
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), oracle.list_rank_weighted(succ, w))
+    n = 200_003
+    succ = W.random_list(n, 71)
+    z = np.zeros(n, np.int32)
+    assert (pj.list_rank_weighted(dev(succ), dev(z)).cpu().numpy() == 0).all()
+    w = np.random.default_rng(72).integers(0, 10_000, n).astype(np.int32)  # total < 2^31
+    got = pj.list_rank_weighted(dev(succ), dev(w), max_walk=16, spacing=4096, cutoff=64)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.list_rank_weighted(succ, w))
+    sizes = [0, 1, 0, 5, 1, 0, 3000, 0]
+    parts = [W.random_list(k, 73 + i) if k else np.empty(0, np.int32) for i, k in enumerate(sizes)]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    cat = np.concatenate(parts).astype(np.int32)
+    wc = np.random.default_rng(74).integers(-50, 50, cat.shape[0]).astype(np.int32)
+    want = np.concatenate([oracle.list_rank_weighted(p, wc[off[i]:off[i + 1]])
+                           for i, p in enumerate(parts)]).astype(np.int32)
+    got = pj.list_rank_weighted_batched(dev(cat), dev(wc), dev(off), h_offsets=off)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
