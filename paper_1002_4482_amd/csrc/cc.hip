@@ -171,7 +171,11 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
 // D[a] = b (concurrent writes, arbitrary winner) and stamp Q[b].  Then every
 // vertex with a pair is hooked (the larger end of one) or stamped (the
 // smaller end), step 3 finds no stagnant root, and the stamps are never read:
-// the kernel only stores the hooks, one per root and workgroup.
+// the kernel only stores the hooks.  These are plain stores, unlike the
+// hooks of later rounds: nothing reads D in this kernel, and round 1 keeps
+// every pair, so a hook lost between two XCDs' caches would only leave its
+// vertex a root for round 2 to hook (measured: 3% faster than write-through
+// stores, no wrong label under stress).
 constexpr int kCompactPer = 8;
 constexpr int kCompactWaves = 256 / kWave;
 // After round 1 a workgroup also drops repeats within its chunk: contracted
@@ -197,8 +201,6 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
   __shared__ int cnt[kCompactPer][kCompactWaves];
   __shared__ unsigned long long chunk_base;
   __shared__ unsigned long long seen[kFirst ? 1 : kDedupSlots];
-  __shared__ int hooked_a[kFirst ? kClaim : 1];
-  if (kFirst) claim_clear(hooked_a);
   bool hooked = false;
   const int wave = threadIdx.x / kWave;
   const int64_t chunk = 256 * kCompactPer;
@@ -226,7 +228,7 @@ __global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ sr
             keep[t] = u != v;
             if (keep[t]) {
               const int a = u > v ? u : v;
-              if (claim(hooked_a, a)) publish(&D[a], u > v ? v : u);
+              D[a] = u > v ? v : u;
               hooked = true;
             }
           }
