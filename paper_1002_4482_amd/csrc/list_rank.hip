@@ -883,6 +883,16 @@ __global__ void chk_perm(const int32_t* __restrict__ cnt, const int64_t* __restr
   }
 }
 
+// Weighted calls with a status: the level sums are weights, not node counts,
+// so the coverage check by the base total does not apply.  Instead every
+// state word starts as "no sublist", and an expansion that meets one (a node
+// no walk reached: a cycle beside the list) reports it.
+__global__ void __launch_bounds__(256) lr_state_clear(int2* __restrict__ state, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    state[i] = make_int2(-1, 0);
+}
+
 // ---------------------------------------------------------------- status
 __global__ void lr_status(const LrCtl* ctl, const int32_t* lerr, const int32_t* ltails,
                           const int64_t* off, int L, int n0, int check_total, int check_tails,
@@ -1232,7 +1242,11 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     }
     PJ_HIP(hipGetLastError());
     tm.mark("headfind");
-    check_total = true;
+    check_total = weight == nullptr;
+    if (weight && status)
+      for (int lv = 0; lv < p.levels; ++lv)
+        hipLaunchKernelGGL(lr_state_clear, dim3(grid_for(p.bound[lv], 256, gcap)), dim3(256), 0,
+                           stream, b.state[lv], p.bound[lv]);
     check_tails = true;
     // walks, level by level
     for (int lv = 0; lv < p.levels; ++lv) {

@@ -483,6 +483,27 @@ def test_weighted_rejects_and_reports(pj):
     dw = dev(w)
     with pytest.raises(Exception):
         pj.list_rank_weighted(dev(succ), dw, dw)
+    # a valid list reports OK through the status (the coverage check compares
+    # the weights the levels saw with the weights given)
+    st = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    got = pj.list_rank_weighted(dev(succ), dev(w), status=st)
+    torch.cuda.synchronize()
+    assert int(st.item()) == pj.PJ_OK
+    assert np.array_equal(got.cpu().numpy(), oracle.list_rank_weighted(succ, w))
+    big = W.random_list(300_007, 55)
+    wb = _weights(300_007, 56)
+    st2 = torch.full((1,), -7, dtype=torch.int32, device="cuda")
+    pj.list_rank_weighted(dev(big), dev(wb), status=st2)
+    torch.cuda.synchronize()
+    assert int(st2.item()) == pj.PJ_OK
+    # a detached cycle beside a shorter list: every node is no longer covered
+    cyc, order = W.random_list_with_order(300_007, 57)
+    cyc = cyc.copy()
+    cyc[order[-1001]] = -1
+    cyc[order[-1]] = order[-1000]
+    pj.list_rank_weighted(dev(cyc), dev(wb), status=st2)
+    torch.cuda.synchronize()
+    assert int(st2.item()) == pj.PJ_EBADLIST
     # malformed list: the status names it
     bad = succ.copy()
     bad[int(np.nonzero(bad != -1)[0][0])] = -1  # a second tail: two lists
