@@ -77,15 +77,12 @@ typedef struct pj_opts {
                                  consecutive node ids (power of two, 2..65536);
                                  zero: n / 2^20 rounded down to a power of
                                  two, within 8..256 for one list and 8..64
-                                 for a batch; 4 for one list below 2^21
-                                 nodes (a single list of >= 2^24 nodes keeps
-                                 8 when most successors are local) */
+                                 for a batch (a single list of >= 2^24 nodes
+                                 keeps 8 when most successors are local) */
     int32_t spacing_up;       /* ruling set, recursion levels: same meaning
                                  (zero: 4) */
     int32_t cutoff;           /* ruling set: a level with at most this many nodes is ranked
-                                 by one workgroup in LDS (64..16384); a whole
-                                 input goes there only if it is a batch of
-                                 more than one list or has at most 4096 nodes */
+                                 by one workgroup in LDS (64..16384) */
     int32_t max_walk;         /* ruling set: a sublist walk is cut after this many nodes,
                                  the cut node becoming a new splitter (>= 16) */
     uint64_t seed;            /* splitter hash seed (results do not depend on it) */
@@ -196,7 +193,7 @@ void pj_graph_cache_clear(void);
 /* ------------------------------------------------------------- autotuner */
 /*
  * Times ruling-set parameters on this input by coordinate descent from the
- * defaults (first-level spacing 4..256, recursion spacing 4..16, LDS cutoff
+ * defaults (first-level spacing 8..256, recursion spacing 4..16, LDS cutoff
  * 2048..16384, workgroup size of the sublist walks 128..1024, each swept with
  * the others at their best so far) and records the fastest in the tune
  * cache, keyed by (gfx arch, ceil(log2 nodes), ceil(log2 lists)).  Later

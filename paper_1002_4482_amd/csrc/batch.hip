@@ -218,7 +218,7 @@ int pj_tune_list_rank(const int32_t* succ, const int64_t* offsets, int64_t L,
   // others held at their best so far (1 warm-up and 3 timed solves each).
   pj::Tuned cur{0, 4, 16384, 1024, 256, 1e30f};
   cur.spacing = pj::list_rank_default_spacing(n0, single);
-  const std::vector<int> sweeps[4] = {{4, 8, 16, 32, 64, 128, 256},
+  const std::vector<int> sweeps[4] = {{8, 16, 32, 64, 128, 256},
                                       {4, 8, 16},
                                       {2048, 4096, 8192, 16384},
                                       {128, 256, 512, 1024}};

@@ -960,8 +960,6 @@ inline int bits_for(int64_t v) {  // bits to hold values 0..v-1
 
 // pack = false keeps level 0 in the separate (sublist, offset) state, which
 // weighted calls need (an offset is then a weight sum, not a step count).
-constexpr int64_t kSmallOne = 4096;
-
 Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o, bool pack = true) {
   Plan p;
   p.algo = o.algo == PJ_ALGO_WYLLIE ? PJ_ALGO_WYLLIE : PJ_ALGO_RULING_SET;
@@ -970,10 +968,7 @@ Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o, bool p
     p.wy_rounds = ilog2((int)std::max<int64_t>(max_size, 1));
     return p;
   }
-  // One workgroup ranks small inputs alone (pointer jumping in LDS); a single
-  // list of more than kSmallOne nodes is faster through the levels (2^14
-  // nodes: 61 against 72 us, measured).
-  if (n0 <= kMaxCutoff && n0 <= o.cutoff && (L > 1 || n0 <= kSmallOne)) {
+  if (n0 <= kMaxCutoff && n0 <= o.cutoff) {
     p.small = true;
     return p;
   }
@@ -1398,9 +1393,6 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
 // early anyway.
 int list_rank_default_spacing(int64_t n, bool single) {
   const int cap = single ? 256 : 64;
-  // below 2^21 nodes one list is latency-bound: shorter walks pay (2^16:
-  // 74 against 82 us, 2^20: 155 against 164 us at spacing 4, measured)
-  if (single && n < (int64_t(1) << 21)) return 4;
   int sp = 8;
   while (sp < cap && (n >> 20) > sp) sp *= 2;
   return sp;

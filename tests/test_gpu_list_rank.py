@@ -293,7 +293,7 @@ def test_autotune_picks_parameters_and_keeps_results(pj, tmp_path):
     d_succ = dev(succ)
     pj.tune_clear()
     best, ms = pj.tune_list_rank(d_succ)
-    assert best["spacing"] in (4, 8, 16, 32, 64, 128, 256) and best["spacing_up"] in (4, 8, 16)
+    assert best["spacing"] in (8, 16, 32, 64, 128, 256) and best["spacing_up"] in (4, 8, 16)
     assert best["cutoff"] in (2048, 4096, 8192, 16384) and best["block"] in (128, 256, 512, 1024)
     assert ms > 0
     assert pj.tune_lookup(n) == best
