@@ -424,6 +424,8 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
 
     ex.update(cc_families(torch, pj, dev, steps))
 
+    ex.update(cc_batched(torch, pj, dev, steps))
+
     # batched lists vs per-list launches
     log("generating 4096 lists, sizes log-uniform in [2^6, 2^20]")
     bs, boff = W.batched_lists(4096, 6, 20, W.SEED_BASE + 4)
@@ -474,6 +476,50 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
     pj.tune_clear()
     ex.update(run_serving(torch, pj, args))
     return ex
+
+
+def cc_batched(torch, pj, dev, steps, G=1024, seed=W.SEED_BASE + 8):
+    """G graphs of the serving mix's shape (n = 2^U, U ~ U[8, 16], degree
+    ~ U[2, 16], uniform pairs) solved by one batched call and by one call per
+    graph; local ids and offset tables as the batched call takes them."""
+    rng = np.random.default_rng(seed)
+    ns = np.floor(2.0 ** rng.uniform(8, 16, G)).astype(np.int64)
+    ms = np.round(ns * rng.uniform(2, 16, G) / 2).astype(np.int64)
+    srcs, dsts = [], []
+    for i in range(G):
+        a, b = W.random_graph(int(ns[i]), int(ms[i]), seed + 1 + i)
+        srcs.append(a)
+        dsts.append(b)
+    voff = np.concatenate([[0], np.cumsum(ns)]).astype(np.int64)
+    eoff = np.concatenate([[0], np.cumsum(ms)]).astype(np.int64)
+    src, dst = np.concatenate(srcs), np.concatenate(dsts)
+    ds, dd = torch.from_numpy(src).to(dev), torch.from_numpy(dst).to(dev)
+    dv, de = torch.from_numpy(voff).to(dev), torch.from_numpy(eoff).to(dev)
+    lab = torch.empty(int(voff[-1]), dtype=torch.int32, device=dev)
+    views = [(ds[eoff[i]:eoff[i + 1]], dd[eoff[i]:eoff[i + 1]], int(ns[i]),
+              lab[voff[i]:voff[i + 1]]) for i in range(G)]
+
+    def batched():
+        pj.connected_components_batched(ds, dd, dv, de, lab, h_vtx_off=voff, h_edge_off=eoff)
+
+    def plain():
+        for a, b, n, out in views:
+            pj.connected_components(a, b, n, out)
+
+    ms_b = timed(torch, batched, steps, 1)
+    got_b = lab.clone()
+    ms_p = timed(torch, plain, 2, 1)
+    same = bool(torch.equal(lab, got_b))
+    log(f"cc batched {G} graphs ({int(voff[-1])} vertices, {int(eoff[-1])} pairs): "
+        f"{ms_b:.3f} ms, one call per graph {ms_p:.3f} ms, identical {same}")
+    if not same:
+        raise SystemExit("batched and per-graph components differ")
+    return {"cc_batched_1024_graphs_vertices": int(voff[-1]),
+            "cc_batched_1024_graphs_pairs": int(eoff[-1]),
+            "cc_batched_1024_graphs_ms": round(ms_b, 3),
+            "cc_batched_1024_graphs_plain_ms": round(ms_p, 3),
+            "cc_batched_1024_graphs_pairs_per_s": round(int(eoff[-1]) / (ms_b * 1e-3), 1),
+            "cc_batched_1024_graphs_speedup_vs_plain": round(ms_p / ms_b, 3)}
 
 
 def cc_families(torch, pj, dev, steps, m=8_000_000, comps=64):
