@@ -110,3 +110,38 @@ def test_python_layer_rejects_short_outputs_and_bad_tables():
     with pytest.raises(ValueError):
         api._need(torch.empty(3, dtype=torch.int32), 4, "rank")
     api._need(torch.empty(4, dtype=torch.int32), 4, "rank")
+
+
+def test_argument_checks_before_any_device_work(lib):
+    # these calls are refused by host-side checks before any HIP call, so they
+    # run without a GPU; the pointers are host memory and never dereferenced
+    from paper_1002_4482_amd import _lib
+    L = _lib.load()
+    EINVAL = -1
+    buf = np.zeros(64, dtype=np.int32)
+    p = buf.ctypes.data
+    o = _lib.PjOpts()
+    L.pj_opts_init(ctypes.byref(o))
+    assert L.pj_list_rank_ex(p, -1, p + 4 * 32, ctypes.byref(o), None) == EINVAL
+    assert L.pj_list_rank_ex(None, 16, p, ctypes.byref(o), None) == EINVAL
+    # partial overlap of rank and succ
+    assert L.pj_list_rank_ex(p, 16, p + 8, ctypes.byref(o), None) == EINVAL
+    # in place is allowed, but not with the full output check
+    o.validate = 1
+    assert L.pj_list_rank_ex(p, 16, p, ctypes.byref(o), None) == EINVAL
+    o.validate = 0
+    # weighted: weights required, no Wyllie, no to-tail form, no full check,
+    # and rank must not overlap the weights
+    w = p + 4 * 16
+    r = p + 4 * 32
+    assert L.pj_list_rank_weighted(p, None, 16, r, ctypes.byref(o), None) == EINVAL
+    for field, value in (("algo", 1), ("to_tail", 1), ("validate", 1)):
+        L.pj_opts_init(ctypes.byref(o))
+        setattr(o, field, value)
+        assert L.pj_list_rank_weighted(p, w, 16, r, ctypes.byref(o), None) == EINVAL, field
+    L.pj_opts_init(ctypes.byref(o))
+    assert L.pj_list_rank_weighted(p, w, 16, w + 4, ctypes.byref(o), None) == EINVAL
+    assert L.pj_list_rank_weighted_batched(p, None, p, 1, r, ctypes.byref(o), None) == EINVAL
+    # weighted workspace is larger than the packed form's
+    assert (L.pj_list_rank_weighted_workspace_bytes(1 << 20, 1, None)
+            > L.pj_list_rank_workspace_bytes(1 << 20, 1, None))
