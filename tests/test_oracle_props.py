@@ -91,3 +91,23 @@ def test_batched_lists_equal_single_calls(sizes, rnd):
     assert (status == oracle.OK).all()
     for i, s in enumerate(lists):
         assert rank[off[i]:off[i + 1]].tolist() == oracle.list_rank(s).tolist()
+
+
+@settings(max_examples=200, deadline=None)
+@given(st.permutations(list(range(30))).flatmap(
+    lambda p: st.tuples(st.just(p), st.integers(1, 30), st.booleans(),
+                        st.lists(st.integers(-2**31, 2**31 - 1), min_size=30, max_size=30))))
+def test_weighted_ranks_step_by_the_weights(args):
+    # rank[head] = 0 and rank[succ[i]] = rank[i] + weight[i] in 32-bit
+    # two's complement, for any weights (the cpu baseline agrees on unit
+    # weights)
+    perm, n, self_tail, wl = args
+    order = [v for v in perm if v < n]
+    succ = list_from_order(order, self_tail)
+    w = np.array(wl[:n], dtype=np.int64).astype(np.int32)
+    rank = oracle.list_rank_weighted(succ, w).astype(np.int64)
+    assert rank[order[0]] == 0
+    for a, b in zip(order, order[1:]):
+        assert (rank[b] - rank[a] - int(w[a])) % (1 << 32) == 0
+    rc, cpu = oracle.cpu_ruling_set(succ, 4, 3)
+    assert rc == oracle.OK and np.array_equal(cpu, oracle.list_rank(succ))
