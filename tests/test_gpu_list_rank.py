@@ -539,3 +539,13 @@ def test_weighted_edge_cases(pj):
     got = pj.list_rank_weighted_batched(dev(cat), dev(wc), dev(off), h_offsets=off)
     torch.cuda.synchronize()
     assert np.array_equal(got.cpu().numpy(), want)
+
+
+def test_weighted_golden_worked_example(pj):
+    from helpers import read_golden
+    g = read_golden("list_weighted_worked_example.txt")
+    succ = np.array(g["succ"], dtype=np.int32)
+    w = np.array(g["weight"], dtype=np.int32)
+    got = pj.list_rank_weighted(dev(succ), dev(w))
+    torch.cuda.synchronize()
+    assert got.cpu().numpy().tolist() == g["weighted_rank"]

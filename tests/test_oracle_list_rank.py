@@ -158,6 +158,15 @@ def _weighted_brute(order, weight):
     return rank
 
 
+def test_weighted_golden_worked_example():
+    g = read_golden("list_weighted_worked_example.txt")
+    succ = np.array(g["succ"], dtype=np.int32)
+    w = np.array(g["weight"], dtype=np.int32)
+    assert oracle.list_rank_weighted(succ, w).tolist() == g["weighted_rank"]
+    # the paper's own tail marker gives the same ranks
+    assert oracle.list_rank_weighted(W.to_self_loop_tails(succ), w).tolist() == g["weighted_rank"]
+
+
 @pytest.mark.parametrize("n", range(1, 7))
 def test_weighted_every_permutation_brute_force(n):
     rng = np.random.default_rng(n)
