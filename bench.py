@@ -389,6 +389,8 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
         for algo in ("ruling_set", "wyllie"):
             ms = timed(torch, lambda: pj.list_rank(ds, d_rank, algo=algo), steps, 1)
             ex[f"list_2p{args.log2n}_{name}_{algo}_nodes_per_s"] = round(n / (ms * 1e-3), 1)
+            ex[f"list_2p{args.log2n}_{name}_{algo}_frac_of_hbm"] = round(
+                LR_BYTES_PER_NODE * n / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
             log(f"{name} {algo} {ms:.3f} ms")
         del ds
 
@@ -400,6 +402,8 @@ def run_extras(torch, pj, dev, d_succ, d_rank, n, args):
         ms = timed(torch, lambda: pj.list_rank(s1, r1, algo=algo), 20, 3)
         ex[f"list_2p20_uniform_{algo}_nodes_per_s"] = round(n1 / (ms * 1e-3), 1)
         ex[f"list_2p20_uniform_{algo}_ms"] = round(ms, 4)
+        ex[f"list_2p20_uniform_{algo}_frac_of_hbm"] = round(
+            LR_BYTES_PER_NODE * n1 / (ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
         log(f"2^20 uniform {algo} {ms:.4f} ms")
 
     # components
