@@ -252,6 +252,8 @@ def main():
             "sample": "sequential union-find over the whole graph, one run"}
         log(f"CPU components oracle: {dt * 1e3:.1f} ms")
         extras["host_cpu"] = {"model": host_cpu_model(), "threads": os.cpu_count()}
+    extras["environment"] = {"hip": getattr(torch.version, "hip", None), "torch": torch.__version__,
+                             "device": torch.cuda.get_device_name(0), "seed_base": W.SEED_BASE}
 
     out = {
         "metric": METRIC,
