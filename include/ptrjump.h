@@ -262,7 +262,9 @@ typedef struct pj_server pj_server;
 
 typedef struct pj_server_config {
     size_t hbm_budget;      /* device bytes all in-flight ticks may hold (0 = 16 GiB) */
-    int32_t max_inflight;   /* ticks on the device at once, one worker and stream each (0 = 3) */
+    int32_t max_inflight;   /* ticks on the device at once, one worker and stream each (0 = 3);
+                               more workers than the device's hardware queues (4 by
+                               default) share queues and lose throughput */
     int32_t max_batch;      /* requests per tick (0 = 256) */
     int32_t device;         /* HIP device (-1 = the calling thread's current device) */
     int32_t reserved;
