@@ -185,12 +185,34 @@ __global__ void __launch_bounds__(256) lr_headfind_batched(const int32_t* __rest
   const int nwaves = (gridDim.x * blockDim.x) / kWave;
   const int lane = lane_id();
   const int chunk = kWave * kHfChunk;
-  for (int64_t c0 = (int64_t)wave * chunk; c0 < n; c0 += (int64_t)nwaves * chunk) {
-    int l = find_instance(off, L, c0);
+  // each wave owns a contiguous run of chunks: one search of the offset
+  // table per wave, then every lane follows the list boundaries forward
+  const int64_t nchunks = ((int64_t)n + chunk - 1) / chunk;
+  const int64_t per = (nchunks + nwaves - 1) / nwaves;
+  const int64_t ci0 = (int64_t)wave * per;
+  const int64_t ci1 = ci0 + per < nchunks ? ci0 + per : nchunks;
+  int l = ci0 < ci1 ? find_instance(off, L, ci0 * chunk) : 0;
+  for (int64_t ci = ci0; ci < ci1; ++ci) {
+    const int64_t c0 = ci * chunk;
     int64_t lend = off[l + 1];
     int64_t lbase = off[l];
     unsigned long long acc = 0;
     int tails = 0;
+    // all loads (and the copy) of the chunk first: the flushes below hold
+    // atomics that would otherwise keep each load waiting for the last
+    int sv[kHfChunk];
+#pragma unroll
+    for (int t = 0; t < kHfChunk; ++t) {
+      const int64_t g = c0 + t * kWave + lane;
+      sv[t] = g < n ? succ[g] : 0;
+    }
+    if (kCopy) {
+#pragma unroll
+      for (int t = 0; t < kHfChunk; ++t) {
+        const int64_t g = c0 + t * kWave + lane;
+        if (g < n) copy[g] = sv[t];
+      }
+    }
     for (int t = 0; t < kHfChunk; ++t) {
       int64_t g = c0 + t * kWave + lane;
       if (g >= n) break;
@@ -203,8 +225,7 @@ __global__ void __launch_bounds__(256) lr_headfind_batched(const int32_t* __rest
         lbase = off[l];
         lend = off[l + 1];
       }
-      int s = succ[g];
-      if (kCopy) copy[g] = s;
+      const int s = sv[t];
       int x = (int)(g - lbase);
       int size = (int)(lend - lbase);
       bool tail = (s == -1) | (s == x);
