@@ -796,18 +796,45 @@ __global__ void __launch_bounds__(kBaseThreads) lr_small(const int32_t* succ,
   const int tid = threadIdx.x;
   for (int j = tid; j < n; j += kBaseThreads) lnk[j] = -1;
   __syncthreads();
-  for (int j = tid; j < n; j += kBaseThreads) {
-    const int l = find_instance(off, L, j);
-    const int base = (int)off[l];
-    const int size = (int)(off[l + 1] - base);
-    const int s = succ[j];
-    const bool tail = (s == -1) | (s == j - base);
-    if (tail) {
-      atomicAdd(&ltails[l], 1);
-    } else if ((unsigned)s >= (unsigned)size) {
-      atomicOr(&lerr[l], kErrRange);
-    } else if (atomicExch(&lnk[base + s], j) != -1) {
-      atomicOr(&lerr[l], kErrBase);
+  // Thread t reads the kPerThread consecutive ids from t * kPerThread, all
+  // loads first, and follows the list boundaries forward (one search of the
+  // offset table per thread).
+  const int j0 = tid * kPerThread;
+  if (j0 < n) {
+    int sv[kPerThread];
+    if (j0 + kPerThread <= n && (reinterpret_cast<uintptr_t>(succ) & 15) == 0) {
+      const int4* s4 = reinterpret_cast<const int4*>(succ + j0);
+#pragma unroll
+      for (int q = 0; q < kPerThread / 4; ++q) {
+        const int4 v = s4[q];
+        sv[4 * q] = v.x;
+        sv[4 * q + 1] = v.y;
+        sv[4 * q + 2] = v.z;
+        sv[4 * q + 3] = v.w;
+      }
+    } else {
+#pragma unroll
+      for (int t = 0; t < kPerThread; ++t) sv[t] = j0 + t < n ? succ[j0 + t] : -1;
+    }
+    int l = find_instance(off, L, j0);
+    int base = (int)off[l], end = (int)off[l + 1];
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = j0 + t;
+      if (j >= n) break;
+      while (j >= end) {
+        ++l;
+        base = end;
+        end = (int)off[l + 1];
+      }
+      const int s = sv[t];
+      const bool tail = (s == -1) | (s == j - base);
+      if (tail) {
+        atomicAdd(&ltails[l], 1);
+      } else if ((unsigned)s >= (unsigned)(end - base)) {
+        atomicOr(&lerr[l], kErrRange);
+      } else if (atomicExch(&lnk[base + s], j) != -1) {
+        atomicOr(&lerr[l], kErrBase);
+      }
     }
   }
   __syncthreads();
@@ -844,12 +871,21 @@ __global__ void __launch_bounds__(kBaseThreads) lr_small(const int32_t* succ,
     }
     __syncthreads();
   }
-  for (int j = tid; j < n; j += kBaseThreads) {
-    const int l = find_instance(off, L, j);
-    const int size = (int)(off[l + 1] - off[l]);
-    if (lnk[j] != -1) atomicOr(&lerr[l], kErrBase);
-    const int v = pre[j];
-    rank[j] = to_tail ? size - 1 - v : v;
+  if (j0 < n) {
+    int l = find_instance(off, L, j0);
+    int base = (int)off[l], end = (int)off[l + 1];
+    for (int t = 0; t < kPerThread; ++t) {
+      const int j = j0 + t;
+      if (j >= n) break;
+      while (j >= end) {
+        ++l;
+        base = end;
+        end = (int)off[l + 1];
+      }
+      if (lnk[j] != -1) atomicOr(&lerr[l], kErrBase);
+      const int v = pre[j];
+      rank[j] = to_tail ? end - base - 1 - v : v;
+    }
   }
 }
 
