@@ -477,16 +477,43 @@ __global__ void __launch_bounds__(256) cc_globalise(const int32_t* __restrict__ 
                                                     int64_t m, int32_t* __restrict__ gsrc,
                                                     int32_t* __restrict__ gdst,
                                                     int32_t* __restrict__ gerr) {
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int g = find_instance(eoff, G, e);
-    const int64_t base = voff[g];
-    const int64_t size = voff[g + 1] - base;
-    const int u = src[e], v = dst[e];
-    const bool ok = (unsigned)u < (uint64_t)size && (unsigned)v < (uint64_t)size;
-    gsrc[e] = ok ? (int)(base + u) : -1;
-    gdst[e] = ok ? (int)(base + v) : -1;
-    if (!ok) gerr[g] = 1;
+  // Each wave owns a contiguous run of chunks of kWave * kGlobPer pairs: one
+  // search of the offset table per wave, then every lane follows the graph
+  // boundaries forward.  A chunk's loads are all issued before use.
+  constexpr int kGlobPer = 16;
+  constexpr int64_t kChunk = kWave * kGlobPer;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nwaves = (gridDim.x * blockDim.x) / kWave;
+  const int lane = lane_id();
+  const int64_t nchunks = (m + kChunk - 1) / kChunk;
+  const int64_t per = (nchunks + nwaves - 1) / nwaves;
+  const int64_t ci0 = (int64_t)wave * per;
+  const int64_t ci1 = ci0 + per < nchunks ? ci0 + per : nchunks;
+  if (ci0 >= ci1) return;
+  int g = find_instance(eoff, G, ci0 * kChunk);
+  int64_t gend = eoff[g + 1], base = voff[g], size = voff[g + 1] - base;
+  for (int64_t ci = ci0; ci < ci1; ++ci) {
+    int us[kGlobPer], vs[kGlobPer];
+#pragma unroll
+    for (int t = 0; t < kGlobPer; ++t) {
+      const int64_t e = ci * kChunk + t * kWave + lane;
+      us[t] = e < m ? src[e] : 0;
+      vs[t] = e < m ? dst[e] : 0;
+    }
+    for (int t = 0; t < kGlobPer; ++t) {
+      const int64_t e = ci * kChunk + t * kWave + lane;
+      if (e >= m) break;
+      while (e >= gend) {  // later graphs (empty ones skipped)
+        ++g;
+        gend = eoff[g + 1];
+        base = voff[g];
+        size = voff[g + 1] - base;
+      }
+      const bool ok = (unsigned)us[t] < (uint64_t)size && (unsigned)vs[t] < (uint64_t)size;
+      gsrc[e] = ok ? (int)(base + us[t]) : -1;
+      gdst[e] = ok ? (int)(base + vs[t]) : -1;
+      if (!ok) publish(&gerr[g], 1);  // flags of other graphs share the line
+    }
   }
 }
 
