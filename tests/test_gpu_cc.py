@@ -169,3 +169,36 @@ def test_repeated_solves_are_always_correct(pj):
         torch.cuda.synchronize()
         got = got.cpu().numpy()
         assert np.array_equal(got[:n8], w8) and np.array_equal(got[n8:], w8), rep
+
+
+def test_batched_out_of_range_pairs_are_charged_to_their_graph(pj):
+    # empty graphs between the others exercise the boundary walk of the pair
+    # rewrite; graphs 5 and 200 get one pair out of their own range
+    rng = np.random.default_rng(9)
+    graphs = []
+    for g in range(260):
+        n = 0 if g % 37 == 3 else int(np.floor(2 ** rng.uniform(0, 12)))
+        m = int(n * rng.uniform(0, 6))
+        s, d = W.random_graph(n, m, 5000 + g)
+        graphs.append((n, s.copy(), d.copy()))
+    bad = [g for g in (5, 200) if graphs[g][0] > 0 and len(graphs[g][1]) > 0]
+    for g in bad:
+        graphs[g][2][len(graphs[g][2]) // 2] = graphs[g][0] + 3
+    voff = np.zeros(len(graphs) + 1, np.int64)
+    eoff = np.zeros(len(graphs) + 1, np.int64)
+    voff[1:] = np.cumsum([g[0] for g in graphs])
+    eoff[1:] = np.cumsum([len(g[1]) for g in graphs])
+    src = np.concatenate([g[1] for g in graphs]).astype(np.int32)
+    dst = np.concatenate([g[2] for g in graphs]).astype(np.int32)
+    st = torch.full((len(graphs),), -9, dtype=torch.int32, device="cuda")
+    got = pj.connected_components_batched(dev(src), dev(dst), dev(voff), dev(eoff),
+                                          h_vtx_off=voff, h_edge_off=eoff, status=st)
+    torch.cuda.synchronize()
+    status = st.cpu().numpy()
+    got = got.cpu().numpy()
+    for g, (n, s, d) in enumerate(graphs):
+        if g in bad:
+            assert status[g] == pj.PJ_EINVAL, g
+        else:
+            assert status[g] == pj.PJ_OK, g
+            assert np.array_equal(got[voff[g]:voff[g + 1]], oracle.connected_components(s, d, n)), g
