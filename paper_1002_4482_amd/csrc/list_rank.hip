@@ -716,6 +716,40 @@ __global__ void __launch_bounds__(256) lr_expand0(const int2* __restrict__ state
   if (bad) atomicOr(&ctl->err, kErrTotal);
 }
 
+// ------------------------------------------------ per-node batched passes
+// Calls f(g, l, base, size) for every node g of a batch, with l its list.
+// Each wave owns a contiguous run of chunks of kWave * kListedPer nodes: one
+// search of the offset table per wave, then every lane follows the list
+// boundaries forward (a search per node costs a chain of dependent loads).
+// Lanes of a wave touch consecutive nodes, so accesses stay coalesced.
+constexpr int kListedPer = 16;
+template <class F>
+__device__ __forceinline__ void for_each_listed(const int64_t* __restrict__ off, int L, int64_t n,
+                                                F f) {
+  constexpr int64_t kChunk = kWave * kListedPer;
+  const int wave = (blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const int nwaves = (gridDim.x * blockDim.x) / kWave;
+  const int lane = lane_id();
+  const int64_t nchunks = (n + kChunk - 1) / kChunk;
+  const int64_t per = (nchunks + nwaves - 1) / nwaves;
+  const int64_t ci0 = (int64_t)wave * per;
+  const int64_t ci1 = ci0 + per < nchunks ? ci0 + per : nchunks;
+  if (ci0 >= ci1) return;
+  int l = find_instance(off, L, ci0 * kChunk);
+  int64_t base = off[l], end = off[l + 1];
+  for (int64_t ci = ci0; ci < ci1; ++ci)
+    for (int t = 0; t < kListedPer; ++t) {
+      const int64_t g = ci * kChunk + t * kWave + lane;
+      if (g >= n) break;
+      while (g >= end) {  // later lists (empty ones skipped)
+        ++l;
+        base = end;
+        end = off[l + 1];
+      }
+      f(g, l, base, (int)(end - base));
+    }
+}
+
 // --------------------------------------------------------------- Wyllie
 // Pointer jumping (Section 3.1) on packed (distance to tail, next) pairs:
 // one 64-bit read of the node's own pair, one 64-bit gather of its next's
@@ -731,15 +765,7 @@ __global__ void __launch_bounds__(1024) wy_init(const int32_t* __restrict__ succ
                                                 const int64_t* __restrict__ off, int L, int n,
                                                 unsigned long long* __restrict__ pair,
                                                 int32_t* lerr) {
-  const int stride = gridDim.x * blockDim.x;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
-    int64_t base = 0;
-    int size = n, l = 0;
-    if (kBatched) {
-      l = find_instance(off, L, g);
-      base = off[l];
-      size = (int)(off[l + 1] - base);
-    }
+  auto one = [&](int64_t g, int l, int64_t base, int size) {
     const int s = succ[g];
     const int xl = (int)(g - base);
     bool tail = (s == -1) | (s == xl);
@@ -748,6 +774,12 @@ __global__ void __launch_bounds__(1024) wy_init(const int32_t* __restrict__ succ
       tail = true;
     }
     pair[g] = tail ? pack_dn(0, -1) : pack_dn(1, (int)(base + s));
+  };
+  if (kBatched) {
+    for_each_listed(off, L, n, one);
+  } else {
+    const int stride = gridDim.x * blockDim.x;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) one(g, 0, 0, n);
   }
 }
 
@@ -766,17 +798,17 @@ template <bool kBatched, bool kToTail>
 __global__ void __launch_bounds__(1024) wy_final(const unsigned long long* __restrict__ pair,
                                                  const int64_t* __restrict__ off, int L, int n,
                                                  int32_t* __restrict__ rank, int32_t* lerr) {
-  const int stride = gridDim.x * blockDim.x;
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) {
+  auto one = [&](int64_t g, int l, int64_t, int size) {
     const unsigned long long v = pair[g];
     const int dist = (int)(v >> 32);
-    int l = 0, size = n;
-    if (kBatched) {
-      l = find_instance(off, L, g);
-      size = (int)(off[l + 1] - off[l]);
-    }
     if ((int)(unsigned)v != -1) atomicOr(&lerr[l], kErrBase);
     rank[g] = kToTail ? dist : size - 1 - dist;
+  };
+  if (kBatched) {
+    for_each_listed(off, L, n, one);
+  } else {
+    const int stride = gridDim.x * blockDim.x;
+    for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += stride) one(g, 0, 0, n);
   }
 }
 
@@ -901,31 +933,35 @@ template <bool kBatched>
 __global__ void chk_count(const int32_t* __restrict__ succ, const int32_t* __restrict__ rank,
                           const int64_t* __restrict__ off, int L, int n, int to_tail,
                           int32_t* cnt, int32_t* lerr) {
-  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
-    int64_t base = 0;
-    int size = n, l = 0;
-    if (kBatched) {
-      l = find_instance(off, L, g);
-      base = off[l];
-      size = (int)(off[l + 1] - base);
-    }
+  auto one = [&](int64_t g, int l, int64_t base, int size) {
     int r = rank[g];
     if (to_tail) r = size - 1 - r;
     if ((unsigned)r >= (unsigned)size) {
       atomicOr(&lerr[l], kErrCheck);
-      continue;
+      return;
     }
     atomicAdd(&cnt[base + r], 1);
     const int s = succ[g];
     const int xl = (int)(g - base);
-    if (s == -1 || s == xl) continue;
+    if (s == -1 || s == xl) return;
     if ((unsigned)s >= (unsigned)size) {
       atomicOr(&lerr[l], kErrCheck);
-      continue;
+      return;
     }
     int rs = rank[base + s];
     if (to_tail) rs = size - 1 - rs;
     if (rs != r + 1) atomicOr(&lerr[l], kErrCheck);
+  };
+  // a grid-stride sweep, not for_each_listed: all waves then work in one
+  // window of the batch, whose ranks the random gathers above find in cache
+  // (contiguous runs per wave were slower: 27.7 against 17.6 ms on 4096 lists)
+  for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < n; g += gridDim.x * blockDim.x) {
+    if (kBatched) {
+      const int l = find_instance(off, L, g);
+      one(g, l, off[l], (int)(off[l + 1] - off[l]));
+    } else {
+      one(g, 0, 0, n);
+    }
   }
 }
 
