@@ -642,7 +642,8 @@ def run_serving(torch, pj, args):
                   for a, b, n, r in pool["cc"]]
     ex = {}
     serve_run(torch, S, pool, args.serve_warmup, None, 1, 16 << 30, check=False)  # warm-up
-    sat = serve_run(torch, S, pool, 300, None, 2, 16 << 30)
+    # a burst long enough to reach steady state (short bursts overstate it)
+    sat = serve_run(torch, S, pool, 1500, None, 2, 16 << 30)
     ex["serving_saturation_req_per_s"] = round(sat["req_per_s"], 1)
     log(f"serving saturation {sat['req_per_s']:.1f} req/s")
     # open-loop Poisson arrivals at fractions of the saturation rate; 0.75 is
