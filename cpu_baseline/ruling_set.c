@@ -3,10 +3,9 @@
  * baseline for the paper's quad-core CPU runs (Section 3.2's sparse ruling
  * set, executed by POSIX threads on the host's cores).
  *
- * TEST AND BENCHMARK INFRASTRUCTURE ONLY, and not a parity reference: the
- * parity reference is oracle_list_rank (oracle.c), against which the tests
- * pin this function.  Nothing in the GPU library includes, links or calls
- * this file.
+ * BENCHMARK INFRASTRUCTURE, and not a parity reference: the tests pin this
+ * function against the CPU oracle's ranks.  It shares no code with the
+ * oracle or the GPU library; neither includes, links or calls it.
  *
  * Steps, each a parallel pass over node ranges or a shared splitter counter:
  *   1. head = n(n-1)/2 - sum of the non-tail successors (every node but the

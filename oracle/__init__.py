@@ -15,8 +15,6 @@ The arithmetic lives in `oracle.c` (plain sequential C, built with gcc by
   connected_components(..) smallest vertex id of each component, per the
                            connected-components problem statement (Section 4).
   *_batched                the same per instance of an offset-table batch.
-  cpu_ruling_set(..)       not a reference: the multi-threaded CPU ruling-set
-                           baseline that the benchmark times beside the GPU.
 
 Parity status: pinned (brute force on small inputs, closed forms of the
 generators, complete invariants and a library cross-check; see tests/).
@@ -56,8 +54,6 @@ def _load():
     lib.oracle_list_rank.restype = ctypes.c_int
     lib.oracle_list_rank_weighted.argtypes = [i32p, i32p, ctypes.c_int64, i32p]
     lib.oracle_list_rank_weighted.restype = ctypes.c_int
-    lib.cpu_ruling_set_list_rank.argtypes = [i32p, ctypes.c_int64, i32p, ctypes.c_int, ctypes.c_int]
-    lib.cpu_ruling_set_list_rank.restype = ctypes.c_int
     lib.oracle_cc.argtypes = [i32p, i32p, ctypes.c_int64, ctypes.c_int64, i32p]
     lib.oracle_cc.restype = ctypes.c_int
     lib.oracle_list_rank_batched.argtypes = [i32p, i64p, ctypes.c_int64, i32p, i32p, ctypes.c_int]
@@ -106,16 +102,6 @@ def list_rank_weighted(succ, weight):
     if rc != OK:
         raise OracleError(rc)
     return rank
-
-
-def cpu_ruling_set(succ, spacing=64, nthreads=None):
-    """(status, rank): the multi-threaded CPU random-splitter baseline
-    (cpu_baseline.c), a comparison point for timing, not a parity reference."""
-    succ = _i32(succ)
-    rank = np.full(succ.shape[0], -1, dtype=np.int32)
-    nt = nthreads or min(16, os.cpu_count() or 1)
-    rc = _load().cpu_ruling_set_list_rank(_p32(succ), succ.shape[0], _p32(rank), spacing, nt)
-    return rc, rank
 
 
 def connected_components(src, dst, n):

@@ -1,4 +1,4 @@
-"""Build the CPU oracle and the CPU baseline (plain C) with gcc into oracle/liboracle.so."""
+"""Build the CPU oracle (plain C) with gcc into oracle/liboracle.so."""
 
 import os
 import subprocess
@@ -7,9 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 
 def build(verbose=False):
-    # oracle.c: the parity reference; cpu_baseline.c: the multi-threaded CPU
-    # comparison baseline (pinned against the reference by the tests)
-    srcs = [os.path.join(HERE, f) for f in ("oracle.c", "cpu_baseline.c")]
+    srcs = [os.path.join(HERE, "oracle.c")]
     out = os.path.join(HERE, "liboracle.so")
     tmp = out + ".tmp"
     cmd = ["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-shared", "-pthread",

@@ -1,9 +1,11 @@
-"""The multi-threaded CPU ruling-set baseline (oracle/cpu_baseline.c), which
-the benchmark times beside the GPU path, pinned against the oracle's ranks."""
+"""The multi-threaded CPU ruling-set baseline (cpu_baseline/ruling_set.c),
+which the benchmark times beside the GPU path, pinned against the oracle's
+ranks."""
 
 import numpy as np
 import pytest
 
+import cpu_baseline
 import oracle
 import workloads as W
 
@@ -13,8 +15,8 @@ import workloads as W
 @pytest.mark.parametrize("threads", [1, 5, 16])
 def test_matches_oracle(n, spacing, threads):
     succ = W.random_list(n, 61 + n % 13)
-    rc, rank = oracle.cpu_ruling_set(succ, spacing, threads)
-    assert rc == oracle.OK
+    rc, rank = cpu_baseline.ruling_set(succ, spacing, threads)
+    assert rc == cpu_baseline.OK
     assert np.array_equal(rank, oracle.list_rank(succ))
 
 
@@ -27,8 +29,8 @@ def test_layouts(layout):
         succ = W.blocked_list(n, 4096, 62)
     else:
         succ = W.to_self_loop_tails(W.random_list(n, 63))
-    rc, rank = oracle.cpu_ruling_set(succ, 16, 8)
-    assert rc == oracle.OK and np.array_equal(rank, oracle.list_rank(succ))
+    rc, rank = cpu_baseline.ruling_set(succ, 16, 8)
+    assert rc == cpu_baseline.OK and np.array_equal(rank, oracle.list_rank(succ))
 
 
 @pytest.mark.parametrize("bad", ["two_tails", "no_tail", "out_of_range", "detached_cycle"])
@@ -45,5 +47,5 @@ def test_malformed_rejected(bad):
     else:  # the list stops early; its last 100 nodes close into a cycle
         succ[order[n - 101]] = -1
         succ[order[-1]] = order[n - 100]
-    rc, _ = oracle.cpu_ruling_set(succ, 64, 4)
-    assert rc == oracle.EBADLIST
+    rc, _ = cpu_baseline.ruling_set(succ, 64, 4)
+    assert rc == cpu_baseline.EBADLIST

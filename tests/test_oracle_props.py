@@ -16,6 +16,7 @@ from scipy.sparse.csgraph import connected_components as scipy_cc
 hyp = pytest.importorskip("hypothesis")
 from hypothesis import given, settings, strategies as st  # noqa: E402
 
+import cpu_baseline  # noqa: E402
 import oracle  # noqa: E402
 from helpers import (brute_list_valid, brute_rank_from_head, check_cc_invariants,  # noqa: E402
                      check_rank_invariants)
@@ -99,8 +100,8 @@ def test_batched_lists_equal_single_calls(sizes, rnd):
                         st.lists(st.integers(-2**31, 2**31 - 1), min_size=30, max_size=30))))
 def test_weighted_ranks_step_by_the_weights(args):
     # rank[head] = 0 and rank[succ[i]] = rank[i] + weight[i] in 32-bit
-    # two's complement, for any weights (the cpu baseline agrees on unit
-    # weights)
+    # two's complement, for any weights (the multi-threaded CPU baseline
+    # agrees on unit weights)
     perm, n, self_tail, wl = args
     order = [v for v in perm if v < n]
     succ = list_from_order(order, self_tail)
@@ -109,5 +110,5 @@ def test_weighted_ranks_step_by_the_weights(args):
     assert rank[order[0]] == 0
     for a, b in zip(order, order[1:]):
         assert (rank[b] - rank[a] - int(w[a])) % (1 << 32) == 0
-    rc, cpu = oracle.cpu_ruling_set(succ, 4, 3)
-    assert rc == oracle.OK and np.array_equal(cpu, oracle.list_rank(succ))
+    rc, cpu = cpu_baseline.ruling_set(succ, 4, 3)
+    assert rc == cpu_baseline.OK and np.array_equal(cpu, oracle.list_rank(succ))

@@ -1,5 +1,5 @@
 """The CPU oracle under AddressSanitizer and UndefinedBehaviorSanitizer:
-gcc builds oracle/oracle.c and oracle/cpu_baseline.c with a small C driver
+gcc builds oracle/oracle.c and cpu_baseline/ruling_set.c with a small C driver
 (host code only) and runs it on valid and malformed lists (plain, weighted,
 and the multi-threaded CPU baseline), graphs and both batched forms."""
 
@@ -17,7 +17,7 @@ def test_oracle_is_clean_under_asan_and_ubsan(tmp_path):
     exe = tmp_path / "oracle_sanitized"
     cmd = ["gcc", "-O1", "-g", "-std=c11", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=undefined", "-pthread",
-           os.path.join(ROOT, "oracle", "oracle.c"), os.path.join(ROOT, "oracle", "cpu_baseline.c"),
+           os.path.join(ROOT, "oracle", "oracle.c"), os.path.join(ROOT, "cpu_baseline", "ruling_set.c"),
            os.path.join(ROOT, "tests", "oracle_sanitize_driver.c"), "-o", str(exe)]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0 and "sanitize" in r.stderr and "not supported" in r.stderr:
