@@ -64,6 +64,10 @@ typedef struct ihipStream_t *pj_stream_t;
 #define PJ_ALGO_RULING_SET 2  /* list ranking by random splitters with recursive splitter ranking */
 #define PJ_ALGO_SV 3          /* components: Shiloach-Vishkin hook and shortcut */
 
+/* Level-0 state layout of the ruling set (pj_opts.level0_state). */
+#define PJ_STATE_AUTO 0      /* packed into the output array when the id space allows */
+#define PJ_STATE_SEPARATE 1  /* a separate 8-byte (sublist, offset) array beside the output */
+
 #define PJ_MAX_PHASES 16
 #define PJ_MAX_LEVELS 8
 
@@ -90,13 +94,30 @@ typedef struct pj_opts {
     int32_t to_tail;          /* 1: list ranks count the distance to the tail (the paper's
                                  convention) instead of the distance from the head */
     int32_t rounds_per_check; /* components: rounds enqueued between host convergence checks */
-    int32_t use_graph;        /* batched list ranking: replay a captured hipGraph */
+    int32_t use_graph;        /* batched list ranking and components: replay a captured
+                                 hipGraph (see pj_graph_cache_clear) */
     int32_t *d_status;        /* optional device int32[instances]: PJ_OK / PJ_EBADLIST / PJ_ENOCONV */
     void *workspace;          /* optional caller-owned device workspace */
     size_t workspace_bytes;
     const int64_t *h_offsets;      /* batched: host copy of the (vertex) offset table */
     const int64_t *h_edge_offsets; /* batched components: host copy of the edge offsets */
     struct pj_stats *stats;   /* optional: filled after the call (forces a stream sync) */
+    int32_t level0_state;     /* ruling set: PJ_STATE_AUTO or PJ_STATE_SEPARATE.  Section 3.2
+                                 weighs one packed word per node (one random line read and
+                                 written per step) against narrower fields in separate
+                                 arrays (a second random line per step); the separate form
+                                 asks that question of this chip.  Results do not change. */
+    int32_t reserved0;
+    const int32_t *d_splitters; /* ruling set, one unweighted list: the level-0 splitters
+                                   chosen by the caller (DEVICE int32[n_splitters], distinct
+                                   node ids in [0, n)) instead of the hashed random ones, as in
+                                   Section 3.2's comparison of random against evenly spaced
+                                   splitters.  Needs the packed level-0 state, in place or
+                                   not; the head is added as a splitter by the library.  Ids
+                                   out of range or repeated are reported as PJ_EINVAL through
+                                   d_status (the ranks are then unspecified).  Results do not
+                                   change. */
+    int64_t n_splitters;      /* entries of d_splitters, 1..n */
 } pj_opts;
 
 /* Diagnostics of one call, filled when opts->stats is set. */
@@ -112,6 +133,11 @@ typedef struct pj_stats {
     char phase_name[PJ_MAX_PHASES][24];
     float phase_ms[PJ_MAX_PHASES];  /* device time of each phase (HIP events) */
     int32_t status;               /* first data error found, or PJ_OK */
+    int32_t max_sublist0;         /* ruling set: nodes of the longest level-0 sublist (a
+                                     walk cut at max_walk nodes counts as separate pieces) */
+    int64_t sublists0;            /* ruling set: level-0 sublists (splitters, list heads
+                                     and cut points), i.e. the nodes of level 1 */
+    int64_t cuts0;                /* ruling set: level-0 walks cut at max_walk nodes */
 } pj_stats;
 
 void pj_opts_init(pj_opts *opts);
@@ -182,11 +208,20 @@ size_t pj_list_rank_weighted_workspace_bytes(int64_t total_nodes, int64_t L,
 
 /*
  * Batched list ranking with opts->use_graph = 1 captures the call's whole
- * launch sequence once into a hipGraph (keyed by the buffers, sizes and
- * options; the cache owns the workspace) and replays it with one
- * hipGraphLaunch on later calls.  Not used together with opts->stats or with
- * validate and no d_status.  The cache holds up to 8 graphs;
- * pj_graph_cache_clear() frees them all (it synchronises the device).
+ * launch sequence once into a hipGraph (the cache owns the workspace) and
+ * replays it with one hipGraphLaunch on later calls.  The cache key holds
+ * the device, the succ / offsets / rank / d_status addresses, L, the node
+ * total offsets[L], ceil(log2) of the largest list (Wyllie's round count),
+ * every option field that selects a plan (algo, block, spacing, spacing_up,
+ * cutoff, max_walk, seed, to_tail, validate, level0_state) and the
+ * tune-cache generation.
+ * A replay reads the current contents of succ and of the device offsets, so
+ * the caller may change both between calls: any change the key does not
+ * cover (list sizes with the same total and the same ceil(log2) of the
+ * largest) leaves the captured plan valid.  Not used together with
+ * opts->stats or with validate and no d_status.  The cache holds up to 8
+ * graphs; pj_graph_cache_clear() frees them all (it synchronises the
+ * device).
  */
 void pj_graph_cache_clear(void);
 
@@ -242,6 +277,21 @@ int pj_connected_components_batched_ex(const int32_t *src, const int32_t *dst,
                                        int64_t G, int32_t *label, const pj_opts *opts,
                                        pj_stream_t stream);
 
+/*
+ * Components with opts->use_graph = 1 (plain or batched, not with
+ * opts->stats) capture the solve once into a hipGraph: the batched pair
+ * rewrite and initialisation, the first 8 rounds (a round that follows one
+ * without change returns at once on the device) and the canonicalisation,
+ * which runs only if the solve converged within those rounds.  A call
+ * launches the graph, reads the 8th round's change flag (one stream
+ * synchronisation) and, only if it is raised, finishes the remaining rounds
+ * and the canonicalisation without the graph, on the same state.  The cache
+ * key holds the device, every array address, n, m and G (and whether the
+ * status is read back); the arrays' contents may change between calls.  The
+ * cache owns the workspace and holds up to 8 graphs; pj_graph_cache_clear()
+ * frees them with the list-ranking graphs.
+ */
+
 /* Bytes of workspace a components call needs (G = 1: enough for both the plain
  * call and a batched call holding one graph). */
 size_t pj_cc_workspace_bytes(int64_t n, int64_t m, int64_t G, const pj_opts *opts);
@@ -255,8 +305,11 @@ size_t pj_cc_workspace_bytes(int64_t n, int64_t m, int64_t G, const pj_opts *opt
  * footprint fits in the unused budget; each tick is one batched list ranking
  * plus one batched components solve, run by one of max_inflight worker
  * threads on its own stream, so ticks overlap on the device and requests that
- * arrive meanwhile join the next tick as memory and a worker free up.
- * Results are identical to a solve of the request alone.
+ * arrive meanwhile join the next tick as memory and a worker free up.  A
+ * large request (at least large_items list nodes, or graph vertices plus
+ * pairs) is a tick of its own, and at most max_inflight - 1 such ticks run at
+ * once, so small requests never queue behind a large solve.  Results are
+ * identical to a solve of the request alone.
  */
 typedef struct pj_server pj_server;
 
@@ -268,7 +321,9 @@ typedef struct pj_server_config {
     int32_t max_batch;      /* requests per tick (0 = 256) */
     int32_t device;         /* HIP device (-1 = the calling thread's current device) */
     int32_t reserved;
-    pj_opts opts;           /* solve options; workspace, d_status and stats are ignored */
+    pj_opts opts;           /* solve options; workspace, d_status, stats and d_splitters
+                               are ignored */
+    int64_t large_items;    /* size class boundary (0 = 2^22) */
 } pj_server_config;
 
 typedef struct pj_server_stats {
@@ -282,6 +337,7 @@ typedef struct pj_server_stats {
     double wall_s;           /* first submit to last completion */
     double req_per_s;        /* completed requests per second of wall_s */
     double items_per_s;      /* list nodes + graph pairs per second of wall_s */
+    int64_t large_ticks;     /* ticks formed for one large request */
 } pj_server_stats;
 
 int pj_server_create(const pj_server_config *cfg, pj_server **out);

@@ -25,6 +25,7 @@ PJ_EBUSY = -8
 PJ_ESHUTDOWN = -9
 
 ALGO = {"auto": 0, "wyllie": 1, "ruling_set": 2, "sv": 3}
+LEVEL0_STATE = {"auto": 0, "separate": 1}
 PJ_MAX_PHASES = 16
 PJ_MAX_LEVELS = 8
 
@@ -40,6 +41,9 @@ class PjStats(ctypes.Structure):
         ("phase_name", (ctypes.c_char * 24) * PJ_MAX_PHASES),
         ("phase_ms", ctypes.c_float * PJ_MAX_PHASES),
         ("status", ctypes.c_int32),
+        ("max_sublist0", ctypes.c_int32),
+        ("sublists0", ctypes.c_int64),
+        ("cuts0", ctypes.c_int64),
     ]
 
     def to_dict(self):
@@ -54,6 +58,9 @@ class PjStats(ctypes.Structure):
             "phase_list": [(self.phase_name[i].value.decode(), float(self.phase_ms[i]))
                            for i in range(self.nphases)],
             "status": self.status,
+            "max_sublist0": self.max_sublist0,
+            "sublists0": int(self.sublists0),
+            "cuts0": int(self.cuts0),
         }
 
 
@@ -76,6 +83,10 @@ class PjOpts(ctypes.Structure):
         ("h_offsets", ctypes.c_void_p),
         ("h_edge_offsets", ctypes.c_void_p),
         ("stats", ctypes.POINTER(PjStats)),
+        ("level0_state", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("d_splitters", ctypes.c_void_p),
+        ("n_splitters", ctypes.c_int64),
     ]
 
 
@@ -87,6 +98,7 @@ class PjServerConfig(ctypes.Structure):
         ("device", ctypes.c_int32),
         ("reserved", ctypes.c_int32),
         ("opts", PjOpts),
+        ("large_items", ctypes.c_int64),
     ]
 
 
@@ -107,6 +119,7 @@ class PjServerStats(ctypes.Structure):
         ("wall_s", ctypes.c_double),
         ("req_per_s", ctypes.c_double),
         ("items_per_s", ctypes.c_double),
+        ("large_ticks", ctypes.c_int64),
     ]
 
     def to_dict(self):

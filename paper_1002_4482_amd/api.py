@@ -12,7 +12,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import ALGO, PjError, PjOpts, PjStats
+from ._lib import ALGO, LEVEL0_STATE, PjError, PjOpts, PjStats
 
 
 def _stream_ptr(stream=None):
@@ -57,8 +57,10 @@ def _ptr(t):
 
 def make_opts(algo="auto", block=0, spacing=0, spacing_up=0, cutoff=0, max_walk=0, seed=None,
               validate=False, to_tail=False, rounds_per_check=0, use_graph=False, status=None,
-              workspace=None, h_offsets=None, h_edge_offsets=None, stats=None):
-    """Build a pj_opts.  Host arrays (h_offsets...) must stay alive for the call."""
+              workspace=None, h_offsets=None, h_edge_offsets=None, stats=None,
+              level0_state="auto", splitters=None):
+    """Build a pj_opts.  Host arrays (h_offsets...) and the device `splitters`
+    tensor must stay alive for the call."""
     o = PjOpts()
     _lib.load().pj_opts_init(ctypes.byref(o))
     o.algo = ALGO[algo] if isinstance(algo, str) else int(algo)
@@ -84,6 +86,12 @@ def make_opts(algo="auto", block=0, spacing=0, spacing_up=0, cutoff=0, max_walk=
         o.h_edge_offsets = h_edge_offsets.ctypes.data
     if stats is not None:
         o.stats = ctypes.pointer(stats)
+    o.level0_state = (LEVEL0_STATE[level0_state] if isinstance(level0_state, str)
+                      else int(level0_state))
+    if splitters is not None:
+        splitters = _dev_i32(splitters, "splitters")
+        o.d_splitters = splitters.data_ptr() if splitters.numel() else None
+        o.n_splitters = splitters.numel()
     return o
 
 

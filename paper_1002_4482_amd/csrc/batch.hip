@@ -66,7 +66,7 @@ TuneKey tune_key(int64_t n0, int64_t L) {
 }
 
 // ----------------------------------------------------------- graph cache
-using GraphKey = std::array<int64_t, 18>;
+using GraphKey = std::array<int64_t, 19>;
 struct GraphEntry {
   hipGraphExec_t exec = nullptr;
   void* ws = nullptr;
@@ -108,6 +108,11 @@ void apply_tuned(pj_opts& o, int64_t n0, int64_t L) {
 int graph_batched(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,
                   int32_t* rank, const pj_opts& user, hipStream_t stream) {
   int64_t n0 = h_off[L];
+  // The captured plan depends on the offsets only through the node total, the
+  // list count and (Wyllie) the round count ceil(log2) of the largest list;
+  // the kernels read the offsets' contents at replay time.
+  int64_t max_size = 0;
+  for (int64_t l = 0; l < L; ++l) max_size = std::max(max_size, h_off[l + 1] - h_off[l]);
   int dev = 0;
   PJ_HIP(hipGetDevice(&dev));
   GraphKey key{dev,
@@ -127,7 +132,8 @@ int graph_batched(const int32_t* succ, const int64_t* d_off, int64_t L, const in
                (int64_t)user.seed,
                user.block,
                0,
-               0};
+               bits_for(std::max<int64_t>(max_size, 1)),
+               user.level0_state};
   {
     std::lock_guard<std::mutex> tl(g_tune_mu);
     key[16] = g_tune_gen;  // zero parameters may resolve differently after a retune
@@ -318,9 +324,12 @@ int pj_tune_lookup(int64_t n, int64_t L, pj_opts* out) {
 }
 
 void pj_graph_cache_clear(void) {
-  std::lock_guard<std::mutex> lk(pj::g_graph_mu);
-  for (auto& kv : pj::g_graphs) pj::drop_entry(kv.second);
-  pj::g_graphs.clear();
+  {
+    std::lock_guard<std::mutex> lk(pj::g_graph_mu);
+    for (auto& kv : pj::g_graphs) pj::drop_entry(kv.second);
+    pj::g_graphs.clear();
+  }
+  pj::cc_graph_cache_clear();
 }
 
 }  // extern "C"

@@ -32,7 +32,10 @@
 // strictly smaller ids, step 3 only hooks stars that no step-2 hook touched,
 // and two such stars are never adjacent, so no cycle can form.
 #include <algorithm>
+#include <array>
 #include <cmath>
+#include <map>
+#include <mutex>
 #include <vector>
 
 #include "pj_internal.hpp"
@@ -414,12 +417,20 @@ __global__ void __launch_bounds__(256) sv_stagnant(const int2* __restrict__ pair
 // component costs one atomic per workgroup, not one per vertex.
 constexpr int kCanonPerThread = 8;
 
-__global__ void canon_init(int32_t* __restrict__ M, int n) {
+// The epilogue kernels take `skip`: when it points at a non-zero word (the
+// change flag of the last round a captured graph holds, i.e. the solve has
+// not converged yet), they do nothing and the host finishes the solve.
+__device__ __forceinline__ bool skipped(const int32_t* skip) { return skip && *skip != 0; }
+
+__global__ void canon_init(int32_t* __restrict__ M, int n, const int32_t* skip) {
+  if (skipped(skip)) return;
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) M[v] = v;
 }
 
 __global__ void __launch_bounds__(256) canon_min(const int32_t* __restrict__ D,
-                                                 int32_t* __restrict__ M, int n) {
+                                                 int32_t* __restrict__ M, int n,
+                                                 const int32_t* skip) {
+  if (skipped(skip)) return;
   __shared__ int lead;
   __shared__ int wmin[256 / kWave];
   const int per_block = 256 * kCanonPerThread;
@@ -454,7 +465,8 @@ __global__ void __launch_bounds__(256) canon_min(const int32_t* __restrict__ D,
 template <bool kBatched>
 __global__ void __launch_bounds__(256) canon_label(int32_t* D, const int32_t* __restrict__ M,
                                                    int n, const int64_t* __restrict__ voff,
-                                                   int G) {
+                                                   int G, const int32_t* skip) {
+  if (skipped(skip)) return;
   for (int v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
     int lab = M[D[v]];
     if (kBatched) lab -= (int)voff[find_instance(voff, G, v)];
@@ -520,7 +532,8 @@ __global__ void __launch_bounds__(256) cc_globalise(const int32_t* __restrict__ 
 // Out-of-range pairs are charged to their own graph when the batch records
 // them per graph (gerr); non-convergence concerns the whole solve.
 __global__ void cc_status(const CcCtl* ctl, const int32_t* w, int max_rounds, int G,
-                          const int32_t* gerr, int32_t* status) {
+                          const int32_t* gerr, int32_t* status, const int32_t* skip) {
+  if (skipped(skip)) return;
   const bool noconv = ctl->rounds >= max_rounds && w[max_rounds] != 0;
   const bool range = (ctl->err & kErrRange) != 0;
   for (int g = blockIdx.x * blockDim.x + threadIdx.x; g < G; g += gridDim.x * blockDim.x) {
@@ -589,140 +602,214 @@ size_t cc_carve(int64_t n, int64_t m, int64_t G, bool batched, bool want_status,
   return bytes;
 }
 
-int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const int64_t* d_voff,
-            const int64_t* d_eoff, int64_t G, int32_t* label, const pj_opts* user,
-            hipStream_t stream) {
-  const bool batched = d_voff != nullptr;
-  if (!batched) G = 1;
+// One solve's launch state: the buffers, grid sizes and the arrays the rounds
+// read.  The launch steps below only enqueue work; the eager call and the
+// graph capture compose them differently.
+struct CcRun {
+  int64_t n = 0, m = 0, G = 1;
+  bool batched = false;
+  const int64_t* d_voff = nullptr;
+  const int64_t* d_eoff = nullptr;
+  const int32_t* src = nullptr;
+  const int32_t* dst = nullptr;
+  const int32_t* es = nullptr;  // pairs the rounds read (globalised in a batch)
+  const int32_t* ed = nullptr;
+  int32_t* D = nullptr;         // parent array, in the caller's label buffer
+  int32_t* status = nullptr;
+  int max_rounds = 0, wlen = 0;
+  int ni = 0, gv = 1, gp = 1, gh = 1, gcap = 1;
+  CcBuffers b;
+  hipStream_t stream = nullptr;
+  PhaseTimer* tm = nullptr;
+};
+
+void cc_setup(CcRun& r, const int32_t* src, const int32_t* dst, int64_t n, int64_t m,
+              const int64_t* d_voff, const int64_t* d_eoff, int64_t G, int32_t* label,
+              hipStream_t stream) {
+  r.src = src;
+  r.dst = dst;
+  r.n = n;
+  r.m = m;
+  r.G = G;
+  r.batched = d_voff != nullptr;
+  r.d_voff = d_voff;
+  r.d_eoff = d_eoff;
+  r.D = label;
+  r.stream = stream;
+  r.max_rounds = round_guard(n);
+  r.wlen = r.max_rounds + 2;
+  r.ni = (int)n;
+  r.gcap = device_info().cus * 16;
+  r.gv = grid_for(n, 256, r.gcap);
+  r.gp = grid_for((m + kPairsPer - 1) / kPairsPer, 256, r.gcap);
+  r.gh = grid_for((m + kCompactPer - 1) / kCompactPer, 256, r.gcap);
+}
+
+void mark(CcRun& r, const char* phase) {
+  if (r.tm) r.tm->mark(phase);
+}
+
+// Batched pair rewrite and the state initialisation.
+int cc_prologue(CcRun& r) {
+  CcBuffers& b = r.b;
+  r.es = r.src;
+  r.ed = r.dst;
+  if (r.batched) {
+    hipLaunchKernelGGL(gerr_clear, dim3(grid_for(r.G, 256, 1024)), dim3(256), 0, r.stream, b.gerr,
+                       (int)r.G);
+    if (r.m > 0) {
+      hipLaunchKernelGGL(cc_globalise, dim3(grid_for(r.m, 256, r.gcap)), dim3(256), 0, r.stream,
+                         r.src, r.dst, r.d_voff, r.d_eoff, (int)r.G, r.m, b.gsrc, b.gdst, b.gerr);
+      r.es = b.gsrc;
+      r.ed = b.gdst;
+    }
+  }
+  hipLaunchKernelGGL(sv_init, dim3(r.gv), dim3(256), 0, r.stream, r.D, b.NS, b.Q, r.ni, b.w,
+                     b.mcount, b.stag_any, b.sc_flags, r.wlen, r.wlen * kCompressPasses, b.ctl);
+  PJ_HIP(hipGetLastError());
+  mark(r, "sv0_init");
+  return PJ_OK;
+}
+
+// Round s: every kernel returns at once if an earlier round changed nothing.
+int cc_round(CcRun& r, int s) {
+  CcBuffers& b = r.b;
+  hipStream_t stream = r.stream;
+  int32_t* D = r.D;
+  const int ni = r.ni;
+  // D is the identity in round 1: no shortcut, and mark only records the round
+  if (s > 1)
+    for (int q = 0; q < kCompressPasses; ++q) {
+      int32_t* f = b.sc_flags + (int64_t)s * kCompressPasses + q;
+      hipLaunchKernelGGL(sv_shortcut, dim3(r.gv), dim3(256), 0, stream, D, ni,
+                         (const int32_t*)b.w, s, f, q ? (const int32_t*)(f - 1) : nullptr);
+    }
+  mark(r, "sv1a_shortcut");
+  hipLaunchKernelGGL(sv_mark, dim3(r.gv), dim3(256), 0, stream, D, b.NS, ni, b.w, s, b.ctl);
+  mark(r, "sv1b_mark");
+  if (r.m > 0) {
+    // round 1 reads the input pairs, later rounds the survivors of the last one
+    int2* out = b.pairs[s & 1];
+    if (s == 1)
+      hipLaunchKernelGGL(sv_compact<true>, dim3(r.gh), dim3(256), 0, stream, r.es, r.ed,
+                         (const int2*)nullptr, r.m, (const unsigned long long*)nullptr, D, ni,
+                         out, b.mcount + s, b.w, s, b.ctl);
+    else
+      hipLaunchKernelGGL(sv_compact<false>, dim3(r.gh), dim3(256), 0, stream,
+                         (const int32_t*)nullptr, (const int32_t*)nullptr,
+                         (const int2*)b.pairs[(s - 1) & 1], r.m, b.mcount + (s - 1), D, ni, out,
+                         b.mcount + s, b.w, s, b.ctl);
+    mark(r, "compact");
+    if (s > 1) {  // round 1's steps 2 and 3 are done by its compaction
+      hipLaunchKernelGGL(sv_hook, dim3(r.gp), dim3(256), 0, stream, (const int2*)out,
+                         b.mcount + s, D, b.NS, b.Q, b.w, s);
+      mark(r, "sv2_hook");
+      hipLaunchKernelGGL(sv_stagnant_roots, dim3(r.gv), dim3(256), 0, stream, (const int32_t*)D,
+                         (const int32_t*)b.NS, (const int32_t*)b.Q, ni, b.stag_bits, b.stag_any,
+                         b.w, s);
+      hipLaunchKernelGGL(sv_stagnant, dim3(r.gp), dim3(256), 0, stream, (const int2*)out,
+                         b.mcount + s, D, (const uint64_t*)b.stag_bits,
+                         (const int32_t*)b.stag_any, b.w, s);
+      mark(r, "sv3_stagnant");
+    }
+  }
+  hipLaunchKernelGGL(sv_shortcut, dim3(r.gv), dim3(256), 0, stream, D, ni, (const int32_t*)b.w, s,
+                     (int32_t*)nullptr, (const int32_t*)nullptr);
+  mark(r, "sv4_shortcut");
+  PJ_HIP(hipGetLastError());
+  return PJ_OK;
+}
+
+// Rounds first_round.. with a host convergence check every rounds_per_check
+// rounds, until a round changes nothing or the guard is reached.  Returns the
+// rounds enqueued in all.
+int cc_rounds_eager(CcRun& r, int first_round, int rounds_per_check, int* rounds_out) {
+  PinnedWord pinned;
+  int32_t* hflag = pinned.get();
+  if (!hflag) return PJ_ENOMEM;
+  int rounds = first_round - 1;
+  bool done = r.n == 0 || rounds >= r.max_rounds;
+  while (!done) {
+    const int chunk = std::min(rounds_per_check, r.max_rounds - rounds);
+    for (int c = 0; c < chunk; ++c) PJ_TRY(cc_round(r, ++rounds));
+    PJ_HIP(hipMemcpyAsync(hflag, r.b.w + rounds, sizeof(int32_t), hipMemcpyDeviceToHost,
+                          r.stream));
+    PJ_HIP(hipStreamSynchronize(r.stream));
+    mark(r, "flag_check");
+    if (*hflag == 0 || rounds >= r.max_rounds) done = true;
+  }
+  *rounds_out = rounds;
+  return PJ_OK;
+}
+
+// Canonical labels and the statuses.  skip: see `skipped`.
+int cc_epilogue(CcRun& r, const int32_t* skip) {
+  CcBuffers& b = r.b;
+  if (r.n > 0) {
+    hipLaunchKernelGGL(canon_init, dim3(r.gv), dim3(256), 0, r.stream, b.NS, r.ni, skip);
+    hipLaunchKernelGGL(canon_min, dim3(grid_for(r.n, 256 * kCanonPerThread, r.gcap)), dim3(256),
+                       0, r.stream, (const int32_t*)r.D, b.NS, r.ni, skip);
+    if (r.batched)
+      hipLaunchKernelGGL(canon_label<true>, dim3(r.gv), dim3(256), 0, r.stream, r.D,
+                         (const int32_t*)b.NS, r.ni, r.d_voff, (int)r.G, skip);
+    else
+      hipLaunchKernelGGL(canon_label<false>, dim3(r.gv), dim3(256), 0, r.stream, r.D,
+                         (const int32_t*)b.NS, r.ni, r.d_voff, (int)r.G, skip);
+    PJ_HIP(hipGetLastError());
+    mark(r, "canonicalise");
+  }
+  if (r.status && r.G > 0) {
+    hipLaunchKernelGGL(cc_status, dim3(grid_for(r.G, 256, 1024)), dim3(256), 0, r.stream,
+                       (const CcCtl*)b.ctl, (const int32_t*)b.w, r.max_rounds, (int)r.G,
+                       r.batched ? (const int32_t*)b.gerr : nullptr, r.status, skip);
+    PJ_HIP(hipGetLastError());
+  }
+  return PJ_OK;
+}
+
+int cc_check_args(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, int64_t G,
+                  int32_t* label) {
   if (n < 0 || m < 0 || G < 0 || n >= INT32_MAX || m >= (int64_t(1) << 40)) return PJ_EINVAL;
   if (n > 0 && !label) return PJ_EINVAL;
   if (m > 0 && (!src || !dst)) return PJ_EINVAL;
   if (m > 0 && ((const void*)label == (const void*)src || (const void*)label == (const void*)dst))
     return PJ_EINVAL;
   if (m > 0 && n == 0) return PJ_EINVAL;
+  return PJ_OK;
+}
+
+int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const int64_t* d_voff,
+            const int64_t* d_eoff, int64_t G, int32_t* label, const pj_opts* user,
+            hipStream_t stream) {
+  const bool batched = d_voff != nullptr;
+  if (!batched) G = 1;
+  PJ_TRY(cc_check_args(src, dst, n, m, G, label));
   pj_opts o = resolved_opts(user);
   pj_stats* st = user ? user->stats : nullptr;
   if (st) *st = pj_stats{};
   const bool want_status = o.validate && !o.d_status;
   if (n == 0 && !o.d_status) return PJ_OK;
 
-  const int max_rounds = round_guard(n);
-  const int wlen = max_rounds + 2;
-  CcBuffers b;
-  const size_t need = cc_carve(n, m, G, batched, want_status, wlen, nullptr, &b);
+  CcRun r;
+  cc_setup(r, src, dst, n, m, d_voff, d_eoff, G, label, stream);
+  const size_t need = cc_carve(n, m, G, batched, want_status, r.wlen, nullptr, &r.b);
   Workspace ws;
   PJ_TRY(workspace_acquire(ws, need, &o, stream));
-  cc_carve(n, m, G, batched, want_status, wlen, &ws, &b);
-  int32_t* status = o.d_status ? o.d_status : b.status_tmp;
+  cc_carve(n, m, G, batched, want_status, r.wlen, &ws, &r.b);
+  r.status = o.d_status ? o.d_status : r.b.status_tmp;
 
   PhaseTimer tm;
   PJ_TRY(tm.begin(st != nullptr, stream));
+  r.tm = &tm;
 
-  const int ni = (int)n;
-  const int cus = device_info().cus;
-  const int gcap = cus * 16;
-  const int gv = grid_for(n, 256, gcap);
-  const int gp = grid_for((m + kPairsPer - 1) / kPairsPer, 256, gcap);
-  const int gh = grid_for((m + kCompactPer - 1) / kCompactPer, 256, gcap);
-  int32_t* D = label;
-
-  const int32_t* es = src;
-  const int32_t* ed = dst;
-  if (batched) {
-    hipLaunchKernelGGL(gerr_clear, dim3(grid_for(G, 256, 1024)), dim3(256), 0, stream, b.gerr,
-                       (int)G);
-    if (m > 0) {
-      hipLaunchKernelGGL(cc_globalise, dim3(grid_for(m, 256, gcap)), dim3(256), 0, stream, src,
-                         dst, d_voff, d_eoff, (int)G, m, b.gsrc, b.gdst, b.gerr);
-      es = b.gsrc;
-      ed = b.gdst;
-    }
-  }
-  hipLaunchKernelGGL(sv_init, dim3(gv), dim3(256), 0, stream, D, b.NS, b.Q, ni, b.w, b.mcount,
-                     b.stag_any, b.sc_flags, wlen, wlen * kCompressPasses, b.ctl);
-  PJ_HIP(hipGetLastError());
-  tm.mark("sv0_init");
-
-  // host-visible copy of the change flag
-  PinnedWord pinned;
-  int32_t* hflag = pinned.get();
-  if (!hflag) return PJ_ENOMEM;
+  PJ_TRY(cc_prologue(r));
   int rounds = 0;
-  bool done = n == 0;
+  PJ_TRY(cc_rounds_eager(r, 1, o.rounds_per_check, &rounds));
+  PJ_TRY(cc_epilogue(r, nullptr));
   int result = PJ_OK;
-  while (!done) {
-    const int chunk = std::min(o.rounds_per_check, max_rounds - rounds);
-    for (int c = 0; c < chunk; ++c) {
-      const int s = ++rounds;
-      // D is the identity in round 1: no shortcut, and mark only records the round
-      if (s > 1)
-        for (int q = 0; q < kCompressPasses; ++q) {
-          int32_t* f = b.sc_flags + (int64_t)s * kCompressPasses + q;
-          hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni,
-                             (const int32_t*)b.w, s, f, q ? (const int32_t*)(f - 1) : nullptr);
-        }
-      tm.mark("sv1a_shortcut");
-      hipLaunchKernelGGL(sv_mark, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, b.w, s, b.ctl);
-      tm.mark("sv1b_mark");
-      if (m > 0) {
-        // round 1 reads the input pairs, later rounds the survivors of the last one
-        int2* out = b.pairs[s & 1];
-        if (s == 1)
-          hipLaunchKernelGGL(sv_compact<true>, dim3(gh), dim3(256), 0, stream, es, ed,
-                             (const int2*)nullptr, m, (const unsigned long long*)nullptr, D, ni,
-                             out, b.mcount + s, b.w, s, b.ctl);
-        else
-          hipLaunchKernelGGL(sv_compact<false>, dim3(gh), dim3(256), 0, stream,
-                             (const int32_t*)nullptr, (const int32_t*)nullptr,
-                             (const int2*)b.pairs[(s - 1) & 1], m, b.mcount + (s - 1), D, ni,
-                             out, b.mcount + s, b.w, s, b.ctl);
-        tm.mark("compact");
-        if (s > 1) {  // round 1's steps 2 and 3 are done by its compaction
-          hipLaunchKernelGGL(sv_hook, dim3(gp), dim3(256), 0, stream, (const int2*)out,
-                             b.mcount + s, D, b.NS, b.Q, b.w, s);
-          tm.mark("sv2_hook");
-          hipLaunchKernelGGL(sv_stagnant_roots, dim3(gv), dim3(256), 0, stream,
-                             (const int32_t*)D, (const int32_t*)b.NS, (const int32_t*)b.Q, ni,
-                             b.stag_bits, b.stag_any, b.w, s);
-          hipLaunchKernelGGL(sv_stagnant, dim3(gp), dim3(256), 0, stream, (const int2*)out,
-                             b.mcount + s, D, (const uint64_t*)b.stag_bits,
-                             (const int32_t*)b.stag_any, b.w, s);
-          tm.mark("sv3_stagnant");
-        }
-      }
-      hipLaunchKernelGGL(sv_shortcut, dim3(gv), dim3(256), 0, stream, D, ni, (const int32_t*)b.w,
-                         s, (int32_t*)nullptr, (const int32_t*)nullptr);
-      tm.mark("sv4_shortcut");
-    }
-    PJ_HIP(hipGetLastError());
-    PJ_HIP(hipMemcpyAsync(hflag, b.w + rounds, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
-    PJ_HIP(hipStreamSynchronize(stream));
-    tm.mark("flag_check");
-    if (*hflag == 0) done = true;
-    else if (rounds >= max_rounds) done = true;
-  }
-
-  if (n > 0) {
-    hipLaunchKernelGGL(canon_init, dim3(gv), dim3(256), 0, stream, b.NS, ni);
-    hipLaunchKernelGGL(canon_min, dim3(grid_for(n, 256 * kCanonPerThread, gcap)), dim3(256), 0,
-                       stream, D, b.NS, ni);
-    if (batched)
-      hipLaunchKernelGGL(canon_label<true>, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, d_voff,
-                         (int)G);
-    else
-      hipLaunchKernelGGL(canon_label<false>, dim3(gv), dim3(256), 0, stream, D, b.NS, ni, d_voff,
-                         (int)G);
-    PJ_HIP(hipGetLastError());
-    tm.mark("canonicalise");
-  }
-  if (status && G > 0) {
-    hipLaunchKernelGGL(cc_status, dim3(grid_for(G, 256, 1024)), dim3(256), 0, stream, b.ctl, b.w,
-                       max_rounds, (int)G, batched ? b.gerr : nullptr, status);
-    PJ_HIP(hipGetLastError());
-  }
   if (want_status && G > 0) {
     int32_t hs = 0;
-    PJ_HIP(hipMemcpyAsync(&hs, status, sizeof hs, hipMemcpyDeviceToHost, stream));
+    PJ_HIP(hipMemcpyAsync(&hs, r.status, sizeof hs, hipMemcpyDeviceToHost, stream));
     PJ_HIP(hipStreamSynchronize(stream));
     result = hs;
   }
@@ -730,7 +817,7 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
     PJ_TRY(tm.finish(st));
     st->algo = PJ_ALGO_SV;
     CcCtl hc{};
-    PJ_HIP(hipMemcpyAsync(&hc, b.ctl, sizeof hc, hipMemcpyDeviceToHost, stream));
+    PJ_HIP(hipMemcpyAsync(&hc, r.b.ctl, sizeof hc, hipMemcpyDeviceToHost, stream));
     PJ_HIP(hipStreamSynchronize(stream));
     st->rounds = hc.rounds;
     st->level_nodes[0] = n;
@@ -740,7 +827,146 @@ int cc_impl(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const 
   return result;
 }
 
+// ------------------------------------------------------------ graph replay
+// A components solve captured once into a hipGraph: the prologue, the first
+// kGraphRounds rounds and the epilogue, which does nothing unless the solve
+// converged within those rounds.  Each call launches the graph, reads the
+// last captured round's change flag, and only if it is still raised finishes
+// the remaining rounds and the epilogue eagerly on the same state.  Rounds
+// after convergence return at once on the device.  The cache owns the
+// workspace; the key holds every address and size the capture used.
+constexpr int kGraphRounds = 8;
+
+using CcGraphKey = std::array<int64_t, 14>;
+struct CcGraphEntry {
+  hipGraphExec_t exec = nullptr;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  uint64_t last_used = 0;
+};
+std::mutex g_ccg_mu;
+std::map<CcGraphKey, CcGraphEntry> g_ccg;
+uint64_t g_ccg_clock = 0;
+constexpr size_t kMaxCcGraphs = 8;
+std::map<int, hipStream_t> g_ccg_capture;
+
+void cc_graph_drop(CcGraphEntry& e) {
+  if (e.exec) (void)hipGraphExecDestroy(e.exec);
+  if (e.ws) (void)hipFree(e.ws);
+  e = CcGraphEntry{};
+}
+
+int cc_graph(const int32_t* src, const int32_t* dst, int64_t n, int64_t m, const int64_t* d_voff,
+             const int64_t* d_eoff, int64_t G, int32_t* label, const pj_opts& o,
+             hipStream_t stream) {
+  const bool batched = d_voff != nullptr;
+  if (!batched) G = 1;
+  PJ_TRY(cc_check_args(src, dst, n, m, G, label));
+  const bool want_status = o.validate && !o.d_status;
+  if (n == 0 && !o.d_status) return PJ_OK;
+  int dev = 0;
+  PJ_HIP(hipGetDevice(&dev));
+  const CcGraphKey key{dev,
+                       (int64_t)(uintptr_t)src,
+                       (int64_t)(uintptr_t)dst,
+                       (int64_t)(uintptr_t)d_voff,
+                       (int64_t)(uintptr_t)d_eoff,
+                       (int64_t)(uintptr_t)label,
+                       (int64_t)(uintptr_t)o.d_status,
+                       G,
+                       n,
+                       m,
+                       want_status ? 1 : 0,
+                       kGraphRounds,
+                       0,
+                       0};
+  std::lock_guard<std::mutex> lk(g_ccg_mu);
+  CcRun r;
+  cc_setup(r, src, dst, n, m, d_voff, d_eoff, G, label, stream);
+  auto it = g_ccg.find(key);
+  CcGraphEntry fresh;
+  CcGraphEntry* e = nullptr;
+  if (it != g_ccg.end()) {
+    e = &it->second;
+  } else {
+    if (g_ccg.size() >= kMaxCcGraphs) {  // evict the least recently used
+      auto lru = g_ccg.begin();
+      for (auto j = g_ccg.begin(); j != g_ccg.end(); ++j)
+        if (j->second.last_used < lru->second.last_used) lru = j;
+      cc_graph_drop(lru->second);
+      g_ccg.erase(lru);
+    }
+    fresh.ws_bytes = std::max<size_t>(
+        cc_carve(n, m, G, batched, want_status, r.wlen, nullptr, &r.b), 256);
+    PJ_HIP(hipMalloc(&fresh.ws, fresh.ws_bytes));
+    e = &fresh;
+  }
+  Workspace ws;
+  ws.base = static_cast<char*>(e->ws);
+  ws.size = e->ws_bytes;
+  cc_carve(n, m, G, batched, want_status, r.wlen, &ws, &r.b);
+  r.status = o.d_status ? o.d_status : r.b.status_tmp;
+  const int32_t* last_flag = r.b.w + std::min(kGraphRounds, r.max_rounds);
+  if (it == g_ccg.end()) {
+    hipStream_t& cap = g_ccg_capture[dev];
+    if (!cap && hipStreamCreateWithFlags(&cap, hipStreamNonBlocking) != hipSuccess) {
+      cc_graph_drop(fresh);
+      return PJ_EHIP;
+    }
+    r.stream = cap;
+    hipGraph_t graph = nullptr;
+    hipError_t he = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    int rc = he == hipSuccess ? PJ_OK : PJ_EHIP;
+    if (rc == PJ_OK) rc = cc_prologue(r);
+    for (int s = 1; rc == PJ_OK && s <= std::min(kGraphRounds, r.max_rounds); ++s)
+      rc = cc_round(r, s);
+    if (rc == PJ_OK) rc = cc_epilogue(r, last_flag);
+    if (he == hipSuccess) he = hipStreamEndCapture(cap, &graph);
+    if (rc == PJ_OK && he == hipSuccess)
+      he = hipGraphInstantiate(&fresh.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (rc != PJ_OK || he != hipSuccess) {
+      cc_graph_drop(fresh);
+      if (rc != PJ_OK) return rc;
+      set_last_hip_error(he, "graph capture of components", __FILE__, __LINE__);
+      return PJ_EHIP;
+    }
+    e = &g_ccg.emplace(key, fresh).first->second;
+    r.stream = stream;
+  }
+  e->last_used = ++g_ccg_clock;
+  PJ_HIP(hipGraphLaunch(e->exec, stream));
+  // one host check: did the captured rounds reach convergence?
+  PinnedWord pinned;
+  int32_t* hflag = pinned.get();
+  if (!hflag) return PJ_ENOMEM;
+  PJ_HIP(hipMemcpyAsync(hflag, last_flag, sizeof(int32_t), hipMemcpyDeviceToHost, stream));
+  PJ_HIP(hipStreamSynchronize(stream));
+  if (*hflag != 0) {  // finish eagerly from the next round
+    int rounds = 0;
+    const pj_opts ro = resolved_opts(&o);
+    PJ_TRY(cc_rounds_eager(r, std::min(kGraphRounds, r.max_rounds) + 1, ro.rounds_per_check,
+                           &rounds));
+    PJ_TRY(cc_epilogue(r, nullptr));
+  }
+  int result = PJ_OK;
+  if (want_status && G > 0) {
+    int32_t hs = 0;
+    PJ_HIP(hipMemcpyAsync(&hs, r.status, sizeof hs, hipMemcpyDeviceToHost, stream));
+    PJ_HIP(hipStreamSynchronize(stream));
+    result = hs;
+  }
+  return result;
+}
+
 }  // namespace
+
+void cc_graph_cache_clear() {
+  std::lock_guard<std::mutex> lk(g_ccg_mu);
+  (void)hipDeviceSynchronize();
+  for (auto& kv : g_ccg) cc_graph_drop(kv.second);
+  g_ccg.clear();
+}
 
 size_t cc_workspace(int64_t n, int64_t m, int64_t G, const pj_opts* user, bool batched) {
   pj_opts o = resolved_opts(user);
@@ -754,6 +980,8 @@ extern "C" {
 
 int pj_connected_components_ex(const int32_t* src, const int32_t* dst, int64_t n, int64_t m,
                                int32_t* label, const pj_opts* opts, pj_stream_t stream) {
+  if (opts && opts->use_graph && !opts->stats)
+    return pj::cc_graph(src, dst, n, m, nullptr, nullptr, 1, label, *opts, (hipStream_t)stream);
   return pj::cc_impl(src, dst, n, m, nullptr, nullptr, 1, label, opts, (hipStream_t)stream);
 }
 
@@ -786,6 +1014,8 @@ int pj_connected_components_batched_ex(const int32_t* src, const int32_t* dst,
     n = tmp[0];
     m = tmp[1];
   }
+  if (opts && opts->use_graph && !opts->stats)
+    return pj::cc_graph(src, dst, n, m, vtx_off, edge_off, G, label, *opts, s);
   return pj::cc_impl(src, dst, n, m, vtx_off, edge_off, G, label, opts, s);
 }
 

@@ -454,6 +454,166 @@ __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
   if (errbits) atomicOr(&ctl->err, errbits);
 }
 
+// ------------------------------------------------- caller-chosen splitters
+// Level 0 of one list with the splitters chosen by the caller (Section 3.2's
+// random-versus-even comparison).  "Is y a splitter" is then no longer
+// arithmetic: lr_mark_splitters overwrites each splitter's slot of the
+// successor copy with the mark -(2 + splitter index) and keeps the
+// successor it replaced, and the walk learns that it reached a splitter from
+// the word it reads at the next node anyway.  Distinct ids leave exactly one
+// mark per splitter; a repeated id or one out of range raises kErrSplitter.
+__global__ void __launch_bounds__(256) lr_mark_splitters(int32_t* __restrict__ work,
+                                                         const int32_t* __restrict__ splitters,
+                                                         int r, int n, int32_t* __restrict__ ssucc,
+                                                         int32_t* lerr) {
+  bool bad = false;
+  for (int s = blockIdx.x * blockDim.x + threadIdx.x; s < r; s += gridDim.x * blockDim.x) {
+    const int x = splitters[s];
+    int old = -1;
+    if ((unsigned)x >= (unsigned)n) {
+      bad = true;
+    } else {
+      old = atomicExch(&work[x], -(2 + s));
+      bad |= old <= -2;  // a second mark of one node
+    }
+    ssucc[s] = old;
+  }
+  if (__ballot(bad) && lane_id() == 0) atomicOr(lerr, kErrSplitter);
+}
+
+// The level-0 walk over marked splitters (one list, packed state).  A lane
+// holds the node x it has reached and x's successor word sx, read one step
+// earlier: it writes x's packed state over sx's slot, then reads the word of
+// the successor, which tells whether that node is a splitter (a mark) or
+// gives the next successor.  A splitter's own slot keeps its mark, which is
+// its state (its sublist, offset 0) for the final scatter: the walker that
+// arrives from its predecessor may read the mark at any time during the
+// kernel.  Work distribution and cuts as in lr_walk.
+__global__ void __launch_bounds__(1024) lr_walk_marked(WalkArgs a,
+                                                       const int32_t* __restrict__ splitters,
+                                                       const int32_t* __restrict__ ssucc, int r) {
+  LrCtl* ctl = a.ctl;
+  const int N = ctl->lv[0].n;
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl->lv[0].r = r;
+  const int items = r + 1;  // chosen splitters, then the virtual one at the head
+  int* dyn = &ctl->lv[0].dyn;
+  __shared__ int wg_next;
+  const int per = (int)(((int64_t)items + gridDim.x - 1) / gridDim.x);
+  const int wg_lo = min(items, (int)((int64_t)blockIdx.x * per));
+  const int wg_hi = min(items, wg_lo + per);
+  if (threadIdx.x == 0) wg_next = wg_lo;
+  __syncthreads();
+
+  int sid = -1, x = 0, sx = 0, k = 0, steps = 0;
+  bool at_mark = false;  // x is a chosen splitter: its slot keeps the mark
+  bool retired = false;
+  int errbits = 0;
+  while (true) {
+    const bool need = (sid < 0) & !retired;
+    const uint64_t needm = __ballot(need);
+    if (needm) {
+      const int leader = __builtin_ctzll(needm);
+      int first = 0;
+      if (lane_id() == leader) first = atomicAdd(&wg_next, __popcll(needm));
+      first = __shfl(first, leader);
+      if (need) {
+        const int item = first + lanes_below(needm);
+        if (item >= wg_hi) {
+          retired = true;
+        } else if (item < r) {  // a chosen splitter
+          const int y = splitters[item];
+          if ((unsigned)y >= (unsigned)N) {  // reported by the marking pass
+            store_pair(&a.link_out[item], -1, 0);
+          } else {
+            sid = item;
+            x = y;
+            sx = ssucc[item];
+            k = 0;
+            steps = 0;
+            at_mark = true;
+          }
+        } else {  // the virtual splitter at the head
+          const unsigned long long tri =
+              (unsigned long long)N * (unsigned long long)(N - 1) / 2ull;
+          const long long h = (long long)(tri - a.lsum[0]);
+          if (a.ltails[0] != 1 || h < 0 || h >= N) {
+            atomicOr(&a.lerr[0], a.ltails[0] != 1 ? kErrTails : kErrHead);
+            store_pair(&a.link_out[item], -1, 0);
+          } else {
+            const int v = a.work[(int)h];
+            if (v <= -2) {  // the head is a chosen splitter itself
+              store_pair(&a.link_out[item], -(v + 2), 0);
+            } else {
+              sid = item;
+              x = (int)h;
+              sx = v;
+              k = 0;
+              steps = 0;
+              at_mark = false;
+            }
+          }
+        }
+      }
+    }
+    if (__ballot(!retired) == 0) break;
+    for (int rep = 0; rep < kWalkBurst && sid >= 0; ++rep) {
+      bool tail = (sx == -1) | (sx == x);
+      if (!tail && (unsigned)sx >= (unsigned)N) {
+        atomicOr(&a.lerr[0], kErrRange);
+        tail = true;
+      }
+      if (!at_mark) a.work[x] = (sid << a.kbits) | k;
+      at_mark = false;
+      ++k;
+      if (tail) {
+        store_pair(&a.link_out[sid], -1, k);
+        sid = -1;
+        continue;
+      }
+      const int y = sx;
+      const int v = a.work[y];
+      if (v <= -2) {
+        // (an index past the level's nodes only comes from a malformed input
+        // word, which the head-find pass has reported; level 1 bounds it)
+        store_pair(&a.link_out[sid], -(v + 2), k);
+        sid = -1;
+      } else if (++steps >= a.max_walk) {
+        const int t = atomicAdd(dyn, 1);
+        if (t >= a.cap) {
+          errbits |= kErrOverflow;
+          store_pair(&a.link_out[sid], -1, k);
+          sid = -1;
+        } else {
+          const int nid = r + 1 + t;
+          store_pair(&a.link_out[sid], nid, k);
+          sid = nid;
+          k = 0;
+          steps = 0;
+          x = y;
+          sx = v;
+        }
+      } else {
+        x = y;
+        sx = v;
+      }
+    }
+  }
+  if (errbits) atomicOr(&ctl->err, errbits);
+}
+
+// Longest level-0 sublist (stats only): the largest weight among the level-1
+// nodes, which for unit weights is the node count of each sublist piece.
+__global__ void __launch_bounds__(256) lr_sublist_max(const int2* __restrict__ link,
+                                                      const LrCtl* ctl, int L, int cap0,
+                                                      int32_t* out) {
+  const int N1 = level_nodes(ctl, 1, L, cap0);
+  int mx = 0;
+  for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < N1; j += gridDim.x * blockDim.x)
+    mx = max(mx, link[j].y);
+  mx = -wave_min(-mx);
+  if (lane_id() == 0 && mx > 0) atomicMax(out, mx);
+}
+
 // ------------------------------------------------------------ base: LDS
 // Ranks a weighted forest of at most kMaxCutoff nodes in one workgroup:
 // predecessor links are built in LDS, then pointer jumping along them sums
@@ -688,8 +848,11 @@ __global__ void __launch_bounds__(256) lr_expand0(const int2* __restrict__ state
       s[u] = make_int2(-1, 0);
       if (j < N) {
         if (kPacked) {
+          // a packed (sublist, offset) word, or the mark -(2 + splitter) that
+          // a caller-chosen splitter keeps (its sublist, offset 0)
           const int w = __builtin_nontemporal_load(&rank[j]);
-          s[u] = make_int2((int)((unsigned)w >> kbits), w & ((1 << kbits) - 1));
+          s[u] = w >= 0 ? make_int2((int)((unsigned)w >> kbits), w & ((1 << kbits) - 1))
+                        : make_int2(-(w + 2), 0);
         } else {
           s[u] = state[j];
         }
@@ -996,7 +1159,7 @@ __global__ void lr_status(const LrCtl* ctl, const int32_t* lerr, const int32_t* 
     const int64_t size = off[l + 1] - off[l];
     bool bad = global_bad || lerr[l] != 0;
     if (check_tails && size > 0 && ltails[l] != 1) bad = true;
-    status[l] = bad ? PJ_EBADLIST : PJ_OK;
+    status[l] = (lerr[l] & kErrSplitter) ? PJ_EINVAL : bad ? PJ_EBADLIST : PJ_OK;
   }
 }
 
@@ -1030,6 +1193,7 @@ struct Plan {
   int log2B_far = 0;       // > 0: level 0 may pick this on the device (see lr_walk),
   int kbits_far = 0;       // with these offset bits (packed form)
   int max_walk_far = 0;    // and this cut length
+  int64_t chosen = 0;      // > 0: level 0 uses this many caller-chosen splitters
 };
 
 // rank may be succ itself (in place: the successors are overwritten by the
@@ -1053,7 +1217,10 @@ inline int bits_for(int64_t v) {  // bits to hold values 0..v-1
 
 // pack = false keeps level 0 in the separate (sublist, offset) state, which
 // weighted calls need (an offset is then a weight sum, not a step count).
-Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o, bool pack = true) {
+// chosen > 0: level 0 has that many caller-chosen splitters (never the
+// one-workgroup path, so that they are used).
+Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o, bool pack = true,
+               int64_t chosen = 0) {
   Plan p;
   p.algo = o.algo == PJ_ALGO_WYLLIE ? PJ_ALGO_WYLLIE : PJ_ALGO_RULING_SET;
   p.bound[0] = n0;
@@ -1061,7 +1228,8 @@ Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o, bool p
     p.wy_rounds = ilog2((int)std::max<int64_t>(max_size, 1));
     return p;
   }
-  if (n0 <= kMaxCutoff && n0 <= o.cutoff) {
+  p.chosen = chosen;
+  if (n0 <= kMaxCutoff && n0 <= o.cutoff && chosen == 0) {
     p.small = true;
     return p;
   }
@@ -1081,7 +1249,8 @@ Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o, bool p
     }
     const int spacing = lv == 0 ? o.spacing : o.spacing_up;
     p.log2B[lv] = ilog2(std::max(2, spacing));
-    const int64_t r = (b + (1ll << p.log2B[lv]) - 1) >> p.log2B[lv];
+    const int64_t r = lv == 0 && chosen > 0 ? chosen
+                                            : (b + (1ll << p.log2B[lv]) - 1) >> p.log2B[lv];
     int mw = o.max_walk;
     if (lv == 0) {
       // Pack (sublist id, offset) into 31 bits when the id space allows an
@@ -1112,7 +1281,7 @@ Plan make_plan(int64_t n0, int64_t L, int64_t max_size, const pj_opts& o, bool p
 // are fewer, so the offset may take more bits; the cut length may only grow,
 // which keeps the planned cut-point capacity sufficient.
 void add_far_spacing(Plan& p, int64_t n0, int64_t L, int far, int max_walk) {
-  if (far <= 0 || p.levels < 1 || p.algo != PJ_ALGO_RULING_SET) return;
+  if (far <= 0 || p.levels < 1 || p.algo != PJ_ALGO_RULING_SET || p.chosen > 0) return;
   const int lg = ilog2(far);
   const int64_t r = (n0 + (1ll << lg) - 1) >> lg;
   if (!p.packed) {
@@ -1146,6 +1315,8 @@ struct Buffers {
   unsigned long long* wy_pair = nullptr;
   int32_t* chk = nullptr;
   int32_t* status_tmp = nullptr;
+  int32_t* ssucc = nullptr;           // successors of caller-chosen splitters
+  int32_t* sub_max = nullptr;         // stats: longest level-0 sublist
 };
 
 // Carve (or, with ws == nullptr, just count) the buffers a plan needs.
@@ -1169,6 +1340,8 @@ size_t carve(const Plan& p, int64_t L, bool single, bool validate, bool want_sta
     return bytes;
   }
   if (p.small) return bytes;
+  take(b->sub_max, 1);
+  if (p.chosen > 0) take(b->ssucc, (size_t)p.chosen);
   for (int l = 0; l < p.levels; ++l) {
     if (!(l == 0 && p.packed)) take(b->state[l], (size_t)p.bound[l]);
     take(b->link[l + 1], (size_t)p.bound[l + 1]);
@@ -1235,6 +1408,14 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
   }
   const bool want_status = o.validate && !o.d_status;
   if (n0 == 0 && !o.d_status) return PJ_OK;
+  if (o.level0_state != PJ_STATE_AUTO && o.level0_state != PJ_STATE_SEPARATE) return PJ_EINVAL;
+  // caller-chosen level-0 splitters: one unweighted list, ruling set, the
+  // packed state (the marks live in the successor copy)
+  const int64_t chosen = o.d_splitters && n0 > 0 ? o.n_splitters : 0;
+  if (o.d_splitters && n0 > 0 &&
+      (!single || weight || o.algo == PJ_ALGO_WYLLIE || o.level0_state == PJ_STATE_SEPARATE ||
+       o.n_splitters < 1 || o.n_splitters > n0))
+    return PJ_EINVAL;
 
   int far_spacing = 0;
   {  // ruling-set parameters left at zero come from the tune cache, if tuned
@@ -1248,7 +1429,9 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     o.max_walk = raw.max_walk > 0 ? std::max(raw.max_walk, 16) : o.max_walk;
     if (raw.block > 0) o.block = std::min(1024, (raw.block + 63) / 64 * 64);
   }
-  Plan p = make_plan(n0, L, max_size, o, weight == nullptr);
+  Plan p = make_plan(n0, L, max_size, o,
+                     weight == nullptr && o.level0_state != PJ_STATE_SEPARATE, chosen);
+  if (chosen > 0 && !p.packed) return PJ_EINVAL;  // too many splitters for the packed state
   add_far_spacing(p, n0, L, far_spacing, o.max_walk);
   Buffers b;
   const size_t need = carve(p, L, single, o.validate != 0, want_status, nullptr, &b);
@@ -1334,6 +1517,11 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
                          stream, succ, off, Li, n, copy, b.lsum, b.ltails, b.lerr);
     }
     PJ_HIP(hipGetLastError());
+    if (p.chosen > 0) {
+      hipLaunchKernelGGL(lr_mark_splitters, dim3(grid_for(p.chosen, 256, gcap)), dim3(256), 0,
+                         stream, copy, o.d_splitters, (int)p.chosen, n, b.ssucc, b.lerr);
+      PJ_HIP(hipGetLastError());
+    }
     tm.mark("headfind");
     check_total = weight == nullptr;
     if (weight && status)
@@ -1370,13 +1558,20 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
       if (lv > 0) kfn = lr_walk<false, false, false>;
       else if (single) kfn = p.packed ? lr_walk<true, false, true> : lr_walk<true, false, false>;
       else kfn = p.packed ? lr_walk<true, true, true> : lr_walk<true, true, false>;
-      const int64_t items = ((p.bound[lv] + (1ll << a.log2B) - 1) >> a.log2B) + L;
+      const bool marked = lv == 0 && p.chosen > 0;
+      const int64_t items =
+          marked ? p.chosen + 1 : ((p.bound[lv] + (1ll << a.log2B) - 1) >> a.log2B) + L;
       // workgroup size o.block (tunable): it sets how many lanes share one
       // LDS work counter and contiguous range of splitters
-      int g = persistent_grid((const void*)kfn, blk, 0);
+      int g = marked ? persistent_grid((const void*)lr_walk_marked, blk, 0)
+                     : persistent_grid((const void*)kfn, blk, 0);
       g = (int)std::min<int64_t>(g, (items + blk - 1) / blk);
       if (g < 1) g = 1;
-      hipLaunchKernelGGL(kfn, dim3(g), dim3(blk), 0, stream, a);
+      if (marked)
+        hipLaunchKernelGGL(lr_walk_marked, dim3(g), dim3(blk), 0, stream, a, o.d_splitters,
+                           (const int32_t*)b.ssucc, (int)p.chosen);
+      else
+        hipLaunchKernelGGL(kfn, dim3(g), dim3(blk), 0, stream, a);
       PJ_HIP(hipGetLastError());
       tm.mark(lv == 0 ? "walk0" : "walk_up");
     }
@@ -1464,12 +1659,26 @@ int list_rank_impl(const int32_t* succ, const int64_t* d_off, int64_t L, const i
     st->algo = p.algo;
     st->levels = p.levels;
     st->base_kind = p.small ? 0 : p.base_kind;
+    int32_t hmax = 0;
+    if (p.algo == PJ_ALGO_RULING_SET && !p.small && n0 > 0) {
+      PJ_HIP(hipMemsetAsync(b.sub_max, 0, sizeof(int32_t), stream));
+      hipLaunchKernelGGL(lr_sublist_max, dim3(grid_for(p.bound[1], 256, gcap)), dim3(256), 0,
+                         stream, (const int2*)b.link[1], (const LrCtl*)b.ctl, Li, p.cap[0],
+                         b.sub_max);
+      PJ_HIP(hipGetLastError());
+      PJ_HIP(hipMemcpyAsync(&hmax, b.sub_max, sizeof hmax, hipMemcpyDeviceToHost, stream));
+    }
     LrCtl hc{};
     PJ_HIP(hipMemcpyAsync(&hc, b.ctl, sizeof hc, hipMemcpyDeviceToHost, stream));
     PJ_HIP(hipStreamSynchronize(stream));
     st->level_nodes[0] = n0;
     for (int l = 1; l <= p.levels && l <= PJ_MAX_LEVELS; ++l)
       st->level_nodes[l] = hc.lv[l - 1].r + L + std::min(hc.lv[l - 1].dyn, p.cap[l - 1]);
+    if (p.levels > 0) {
+      st->sublists0 = st->level_nodes[1];
+      st->cuts0 = std::min(hc.lv[0].dyn, p.cap[0]);
+      st->max_sublist0 = hmax;
+    }
     if (p.algo == PJ_ALGO_WYLLIE) st->rounds = n0 > 0 ? p.wy_rounds : 0;
     st->status = result;
   }
@@ -1521,7 +1730,9 @@ size_t list_rank_workspace(int64_t n0, int64_t L, const pj_opts* user, bool sing
   apply_tuned(raw, n0, L);
   (void)level0_spacing(raw.spacing, n0, single, &raw.spacing);
   pj_opts o = resolved_opts(&raw);
-  Plan p = make_plan(n0, L, n0, o, !weighted);
+  const int64_t chosen = o.d_splitters && single && !weighted && n0 > 0
+                             ? std::max<int64_t>(1, std::min(o.n_splitters, n0)) : 0;
+  Plan p = make_plan(n0, L, n0, o, !weighted && o.level0_state != PJ_STATE_SEPARATE, chosen);
   Buffers b;
   return carve(p, L, single, o.validate != 0, o.validate && !o.d_status, nullptr, &b);
 }

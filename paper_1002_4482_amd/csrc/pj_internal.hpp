@@ -25,6 +25,7 @@ enum : int32_t {
   kErrTotal = 32,    // sublists do not cover every node exactly once
   kErrCheck = 64,    // the full output check failed
   kErrNoConv = 128,  // components: round guard reached
+  kErrSplitter = 256,  // a caller-chosen splitter out of range or repeated
 };
 
 void set_last_hip_error(hipError_t e, const char* what, const char* file, int line);
@@ -143,6 +144,9 @@ int level0_spacing(int requested, int64_t n0, bool single, int32_t* planned);
 // Tuned ruling-set parameters for a problem of n0 nodes in L lists, if the
 // tune cache holds an entry for its size class; fills the zero fields of o.
 void apply_tuned(pj_opts& o, int64_t n0, int64_t L);
+
+// Frees the captured components graphs (synchronises the device).
+void cc_graph_cache_clear();
 
 // Batched list ranking through the captured-graph cache (h_off required).
 int graph_batched(const int32_t* succ, const int64_t* d_off, int64_t L, const int64_t* h_off,

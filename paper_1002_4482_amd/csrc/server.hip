@@ -5,6 +5,11 @@
 // waiting requests in arrival order into a "tick" while the tick's exact
 // device footprint (inputs, outputs, offset tables, statuses and the
 // workspace of the two batched solves) fits in the unused part of the budget.
+// Requests are sized into two classes: a large one (at least `large_items`
+// list nodes, or graph vertices plus pairs) gets a tick of its own, and at
+// most max_inflight - 1 large ticks are admitted at once, so one worker is
+// always left for ticks of small requests, which never wait behind a large
+// solve and its host copies.
 // Each tick goes to one of `max_inflight` worker threads, each owning a HIP
 // stream: the worker copies the inputs in, runs one batched list ranking and
 // one batched components solve over all of the tick's requests, copies the
@@ -45,11 +50,31 @@ struct Request {
   double t_submit = 0, t_done = 0;
   int32_t status = PJ_EBUSY;
   bool done = false;
+  bool large = false;     // size class (see Server::large_items)
+  size_t lr_ws1 = 0;      // list ranking: workspace of a solve of this list alone
+};
+
+// Running totals of a tick's requests, from which its footprint follows.
+struct TickSize {
+  int64_t lr_n = 0, lr_L = 0, cc_n = 0, cc_m = 0, cc_G = 0;
+  size_t lr_ws1 = 0;  // largest single-list workspace
+  void add(const Request* r) {
+    if (r->kind == 0) {
+      lr_n += r->n;
+      ++lr_L;
+      lr_ws1 = std::max(lr_ws1, r->lr_ws1);
+    } else {
+      cc_n += r->n;
+      cc_m += r->m;
+      ++cc_G;
+    }
+  }
 };
 
 struct Tick {
   std::vector<Request*> reqs;
   size_t bytes = 0;
+  bool large = false;
 };
 
 size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
@@ -64,6 +89,7 @@ struct Server {
   int max_inflight = 3;
   int max_batch = 256;
   int device = 0;
+  int64_t large_items = int64_t(1) << 22;
   pj_opts opts{};
   // state
   std::mutex mu;
@@ -75,6 +101,9 @@ struct Server {
   std::unordered_map<uint64_t, Request*> reqs;
   size_t used = 0, used_peak = 0;
   int busy_workers = 0, inflight_peak = 0;
+  int large_inflight = 0;              // large ticks ready or running
+  int64_t pending_large = 0;           // large requests not yet admitted
+  int64_t large_ticks = 0;
   bool stopping = false;
   uint64_t next_id = 1;
   Clock::time_point t0 = Clock::now();
@@ -85,35 +114,58 @@ struct Server {
   std::thread sched;
   std::vector<std::thread> workers;
 
-  // Exact device bytes of a tick holding `rs` (must match run_tick's carve).
-  size_t tick_bytes(const std::vector<Request*>& rs) const {
-    int64_t lr_n = 0, lr_L = 0, cc_n = 0, cc_m = 0, cc_G = 0;
-    for (auto* r : rs) {
-      if (r->kind == 0) {
-        lr_n += r->n;
-        ++lr_L;
-      } else {
-        cc_n += r->n;
-        cc_m += r->m;
-        ++cc_G;
-      }
-    }
-    size_t b = 0;
+  // Options of a tick's solves (statuses always written, nothing validated
+  // on the host, the tick's own workspace).
+  pj_opts solve_opts() const {
     pj_opts o = opts;
     o.workspace = nullptr;
+    o.stats = nullptr;
     o.validate = 0;
     o.use_graph = 0;
-    o.d_status = (int32_t*)1;  // statuses are always written
-    if (lr_L) {
-      b += align256(lr_n * 4) * 2 + align256((lr_L + 1) * 8) + align256(lr_L * 4);
-      b += align256(pj_list_rank_workspace_bytes(lr_n, lr_L, &o));
+    o.d_status = (int32_t*)1;
+    return o;
+  }
+
+  // Workspace bytes of a tick's list ranking: the batched solve, and, should
+  // a malformed list make the worker re-solve the tick's lists one by one,
+  // the largest single-list solve (the same region serves both).
+  size_t lr_workspace(const TickSize& z) const {
+    if (z.lr_L == 0) return 0;
+    const pj_opts o = solve_opts();
+    const size_t batched = pj_list_rank_workspace_bytes(z.lr_n, z.lr_L, &o);
+    return align256(z.lr_L > 1 ? std::max(batched, z.lr_ws1) : batched);
+  }
+
+  // Exact device bytes of a tick with these totals (must match run_tick's carve).
+  size_t tick_bytes(const TickSize& z) const {
+    size_t b = 0;
+    const pj_opts o = solve_opts();
+    if (z.lr_L) {
+      b += align256(z.lr_n * 4) * 2 + align256((z.lr_L + 1) * 8) + align256(z.lr_L * 4);
+      b += lr_workspace(z);
     }
-    if (cc_G) {
-      b += align256(cc_m * 4) * 2 + align256(cc_n * 4) + 2 * align256((cc_G + 1) * 8) +
-           align256(cc_G * 4);
-      b += align256(pj_cc_workspace_bytes(cc_n, cc_m, cc_G, &o));
+    if (z.cc_G) {
+      b += align256(z.cc_m * 4) * 2 + align256(z.cc_n * 4) + 2 * align256((z.cc_G + 1) * 8) +
+           align256(z.cc_G * 4);
+      b += align256(pj_cc_workspace_bytes(z.cc_n, z.cc_m, z.cc_G, &o));
     }
     return b;
+  }
+
+  size_t tick_bytes(const std::vector<Request*>& rs) const {
+    TickSize z;
+    for (auto* r : rs) z.add(r);
+    return tick_bytes(z);
+  }
+
+  // A large tick may be admitted while another worker stays free for small ones.
+  bool large_slot_free() const { return max_inflight < 2 || large_inflight < max_inflight - 1; }
+
+  // Some tick can be formed now (memory aside).
+  bool can_form() const {
+    if (pending.empty() || busy_workers + (int)ready.size() >= max_inflight) return false;
+    const int64_t small = (int64_t)pending.size() - pending_large;
+    return small > 0 || (pending_large > 0 && large_slot_free());
   }
 
   void scheduler_loop();
@@ -126,34 +178,71 @@ void Server::scheduler_loop() {
   (void)hipSetDevice(device);
   std::unique_lock<std::mutex> lk(mu);
   for (;;) {
-    cv_sched.wait(lk, [&] {
-      return stopping || (!pending.empty() && busy_workers + (int)ready.size() < max_inflight);
-    });
-    if (stopping && pending.empty()) break;
-    if (pending.empty() || busy_workers + (int)ready.size() >= max_inflight) continue;
-    // form the next tick: requests in arrival order while the footprint fits
-    Tick* t = new Tick;
-    size_t free_bytes = budget - used;
-    while (!pending.empty() && (int)t->reqs.size() < max_batch) {
-      t->reqs.push_back(pending.front());
-      const size_t b = tick_bytes(t->reqs);
-      if (b > free_bytes) {
-        t->reqs.pop_back();
-        break;
+    // Leave the wait only when there is something to do: a tick can be formed,
+    // or the server is stopping with nothing left to admit.  (A predicate that
+    // is true while nothing can be done would spin with the lock held and keep
+    // the workers from retiring their ticks.)
+    cv_sched.wait(lk, [&] { return (stopping && pending.empty()) || can_form(); });
+    if (pending.empty()) break;  // stopping, everything admitted
+    // The oldest large request goes first if it is older than every small
+    // one and a large slot is free; otherwise a tick of small requests in
+    // arrival order (large ones skipped) while the footprint fits.
+    auto first_large = pending.end(), first_small = pending.end();
+    for (auto it = pending.begin(); it != pending.end(); ++it) {
+      if ((*it)->large) {
+        if (first_large == pending.end()) first_large = it;
+      } else if (first_small == pending.end()) {
+        first_small = it;
       }
-      t->bytes = b;
-      pending.pop_front();
+      if (first_large != pending.end() && first_small != pending.end()) break;
+    }
+    const bool pick_large = first_large != pending.end() && large_slot_free() &&
+                            (first_small == pending.end() || (*first_large)->id < (*first_small)->id);
+    Tick* t = new Tick;
+    t->large = pick_large;
+    const size_t free_bytes = budget - used;
+    TickSize z;
+    if (pick_large) {
+      z.add(*first_large);
+      const size_t b = tick_bytes(z);
+      if (b <= free_bytes) {
+        t->reqs.push_back(*first_large);
+        t->bytes = b;
+        pending.erase(first_large);
+        --pending_large;
+      }
+    } else {
+      for (auto it = first_small; it != pending.end() && (int)t->reqs.size() < max_batch;) {
+        if ((*it)->large) {
+          ++it;
+          continue;
+        }
+        TickSize z2 = z;
+        z2.add(*it);
+        const size_t b = tick_bytes(z2);
+        if (b > free_bytes) break;
+        z = z2;
+        t->reqs.push_back(*it);
+        t->bytes = b;
+        it = pending.erase(it);
+      }
     }
     if (t->reqs.empty()) {
-      // the oldest request must wait for memory held by running ticks
+      // The chosen request must wait for memory held by admitted ticks.  It
+      // fits the whole budget (checked at submit), so some tick holds memory
+      // and will release it; stopping changes nothing here.
       delete t;
       ++budget_waits;
-      cv_sched.wait(lk, [&] { return stopping || budget - used != free_bytes; });
+      cv_sched.wait(lk, [&] { return budget - used != free_bytes; });
       continue;
     }
     used += t->bytes;
     used_peak = std::max(used_peak, used);
     ++ticks;
+    if (t->large) {
+      ++large_inflight;
+      ++large_ticks;
+    }
     ready.push_back(t);
     cv_work.notify_one();
   }
@@ -212,6 +301,7 @@ void Server::worker_loop(int idx) {
     finish_tick(t, rc == PJ_OK);
     --busy_workers;
     used -= t->bytes;
+    if (t->large) --large_inflight;
     delete t;
     cv_sched.notify_all();
     cv_done.notify_all();
@@ -261,6 +351,8 @@ int Server::run_tick(Tick* t, hipStream_t s, HostStage& stage) {
   std::copy(eoff.begin(), eoff.end(), h_eoff);
 
   char* d = nullptr;
+  char* lr_ws = nullptr;  // the list-ranking workspace inside the tick's memory
+  size_t lr_ws_bytes = 0;
   int rc = PJ_OK;
   hipError_t he = hipMallocAsync((void**)&d, std::max<size_t>(t->bytes, 256), s);
   if (he != hipSuccess) {
@@ -284,9 +376,12 @@ int Server::run_tick(Tick* t, hipStream_t s, HostStage& stage) {
     int64_t* d_off = (int64_t*)take((L + 1) * 8);
     int32_t* d_st = (int32_t*)take(L * 4);
     o.d_status = d_st;
-    const size_t wsb = pj_list_rank_workspace_bytes(N, L, &o);
-    o.workspace = take(wsb);
-    o.workspace_bytes = align256(wsb);
+    TickSize z;
+    for (auto* r : t->reqs) z.add(r);
+    lr_ws_bytes = lr_workspace(z);
+    lr_ws = take(lr_ws_bytes);
+    o.workspace = lr_ws;
+    o.workspace_bytes = lr_ws_bytes;
     o.h_offsets = h_loff;
     for (int64_t i = 0; i < L && rc == PJ_OK; ++i)
       if (lr[i]->n)
@@ -352,7 +447,8 @@ int Server::run_tick(Tick* t, hipStream_t s, HostStage& stage) {
   if (hipStreamSynchronize(s) != hipSuccess && rc == PJ_OK) rc = PJ_EHIP;
   // A malformed list can raise an error the batched solve cannot pin on one
   // list.  Then each list of the tick is solved again on its own (from the
-  // tick's buffers), so only the malformed requests fail.
+  // tick's buffers and its workspace, sized for the largest single solve),
+  // so only the malformed requests fail.
   bool lr_bad = false;
   for (int64_t i = 0; i < L && rc == PJ_OK; ++i) lr_bad |= h_lst[i] != PJ_OK;
   if (rc == PJ_OK && lr_bad && L > 1) {
@@ -363,7 +459,8 @@ int Server::run_tick(Tick* t, hipStream_t s, HostStage& stage) {
     o1.stats = nullptr;
     o1.use_graph = 0;
     o1.validate = 0;
-    o1.workspace = nullptr;
+    o1.workspace = lr_ws;
+    o1.workspace_bytes = lr_ws_bytes;
     for (int64_t i = 0; i < L && rc == PJ_OK; ++i) {
       o1.d_status = d_st + i;
       rc = pj_list_rank_ex(d_succ + loff[i], lr[i]->n, d_rank + loff[i], &o1, (pj_stream_t)s);
@@ -403,6 +500,7 @@ int pj_server_create(const pj_server_config* cfg, pj_server** out) {
     if (cfg->max_batch > 0) s.max_batch = cfg->max_batch;
     s.opts = cfg->opts;
     s.device = cfg->device;
+    if (cfg->large_items > 0) s.large_items = cfg->large_items;
   } else {
     pj_opts_init(&s.opts);
     s.device = -1;
@@ -412,6 +510,8 @@ int pj_server_create(const pj_server_config* cfg, pj_server** out) {
   s.opts.stats = nullptr;
   s.opts.workspace = nullptr;
   s.opts.d_status = nullptr;
+  s.opts.d_splitters = nullptr;
+  s.opts.n_splitters = 0;
   s.t0 = pj::Clock::now();
   s.sched = std::thread([&s] { s.scheduler_loop(); });
   for (int i = 0; i < s.max_inflight; ++i) s.workers.emplace_back([&s, i] { s.worker_loop(i); });
@@ -431,12 +531,17 @@ static int submit(pj_server* w, int kind, const int32_t* a, const int32_t* b, in
   r->n = n;
   r->m = m;
   r->out = out;
+  r->large = (kind == 0 ? n : n + m) >= s.large_items;
+  if (kind == 0) {
+    const pj_opts o = s.solve_opts();
+    r->lr_ws1 = pj_list_rank_workspace_bytes(n, 1, &o);
+  }
   std::lock_guard<std::mutex> lk(s.mu);
   if (s.stopping) {
     delete r;
     return PJ_ESHUTDOWN;
   }
-  if (s.tick_bytes({r}) > s.budget) {
+  if (s.tick_bytes(std::vector<pj::Request*>{r}) > s.budget) {
     delete r;
     return PJ_EBUDGET;
   }
@@ -445,6 +550,7 @@ static int submit(pj_server* w, int kind, const int32_t* a, const int32_t* b, in
   if (s.first_submit < 0) s.first_submit = r->t_submit;
   s.reqs[r->id] = r;
   s.pending.push_back(r);
+  if (r->large) ++s.pending_large;
   ++s.submitted;
   *id = r->id;
   s.cv_sched.notify_one();
@@ -514,6 +620,7 @@ int pj_server_get_stats(pj_server* w, pj_server_stats* out) {
   out->ticks = s.ticks;
   out->inflight_peak = s.inflight_peak;
   out->budget_waits = s.budget_waits;
+  out->large_ticks = s.large_ticks;
   out->bytes_peak = s.used_peak;
   out->bytes_in_use = s.used;
   std::vector<double> l = s.lat_ms;

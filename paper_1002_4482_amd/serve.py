@@ -42,7 +42,7 @@ def _empty_like_host(n, pinned):
 
 class Server:
     def __init__(self, hbm_budget=16 << 30, max_inflight=3, max_batch=256, device=-1,
-                 pinned_outputs=True, **opt_kw):
+                 pinned_outputs=True, large_items=0, **opt_kw):
         from .api import make_opts
         lib = _lib.load()
         cfg = PjServerConfig()
@@ -50,6 +50,7 @@ class Server:
         cfg.max_inflight = max_inflight
         cfg.max_batch = max_batch
         cfg.device = device
+        cfg.large_items = int(large_items)
         cfg.opts = make_opts(**opt_kw)
         self._h = ctypes.c_void_p()
         rc = lib.pj_server_create(ctypes.byref(cfg), ctypes.byref(self._h))

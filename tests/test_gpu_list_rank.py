@@ -272,6 +272,51 @@ def test_graph_replay_matches_eager_every_time(pj):
     pj.graph_cache_clear()
 
 
+@pytest.mark.parametrize("algo", ["wyllie", "ruling_set"])
+def test_graph_replay_after_list_sizes_change(pj, algo):
+    """Same buffers, same L and the same node total, but the largest list
+    grows past a power of two: Wyllie needs one more jump round than the
+    captured graph ran, so the replay must not reuse it."""
+    L = 4
+    sizes1, sizes2 = [1000, 1000, 1000, 1000], [3980, 10, 5, 5]
+    assert sum(sizes1) == sum(sizes2)
+    total = sum(sizes1)
+
+    def make(sizes, seed):
+        lists = [W.random_list(s, seed + i) for i, s in enumerate(sizes)]
+        return W.concat_lists(lists)
+
+    succ1, off1 = make(sizes1, 300)
+    succ2, off2 = make(sizes2, 400)
+    d_succ = dev(succ1)
+    d_off = dev(off1)
+    out = torch.empty(total, dtype=torch.int32, device="cuda")
+    pj.graph_cache_clear()
+    h_off = off1.copy()
+    for rep in range(2):
+        out.fill_(-1)
+        pj.list_rank_batched(d_succ, d_off, out, h_offsets=h_off, algo=algo, use_graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), oracle.list_rank_batched(succ1, off1)[1]), rep
+    # new sizes written into the same device buffers
+    d_succ.copy_(dev(succ2))
+    d_off.copy_(dev(off2))
+    h_off[:] = off2
+    st = torch.full((L,), 9, dtype=torch.int32, device="cuda")
+    for rep in range(2):
+        out.fill_(-1)
+        pj.list_rank_batched(d_succ, d_off, out, h_offsets=h_off, algo=algo, use_graph=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), oracle.list_rank_batched(succ2, off2)[1]), rep
+    # with statuses (a different graph): a valid batch reports OK everywhere
+    pj.list_rank_batched(d_succ, d_off, out, h_offsets=h_off, algo=algo, use_graph=True,
+                         status=st)
+    torch.cuda.synchronize()
+    assert st.cpu().numpy().tolist() == [0] * L
+    assert np.array_equal(out.cpu().numpy(), oracle.list_rank_batched(succ2, off2)[1])
+    pj.graph_cache_clear()
+
+
 def test_graph_replay_single_large_list(pj):
     n = 3_000_017
     succ = W.random_list(n, 12)
@@ -549,3 +594,129 @@ def test_weighted_golden_worked_example(pj):
     got = pj.list_rank_weighted(dev(succ), dev(w))
     torch.cuda.synchronize()
     assert got.cpu().numpy().tolist() == g["weighted_rank"]
+
+
+# ------------------------------------------- chosen splitters, state layout
+def _chosen(succ, kind, k, seed):
+    """Splitter ids: `kind` "even" takes every k-th node in list order from a
+    random phase; "random" takes n // k distinct nodes uniformly at random."""
+    n = len(succ)
+    order = np.argsort(oracle.list_rank(succ)).astype(np.int32)
+    rng = np.random.default_rng(seed)
+    if kind == "even":
+        return order[int(rng.integers(0, k)) % n::k].copy()
+    return rng.choice(n, max(1, n // k), replace=False).astype(np.int32)
+
+
+@pytest.mark.parametrize("kind", ["even", "random"])
+@pytest.mark.parametrize("n,k", [(20_000, 2), (20_000, 1000), (300_007, 16), (300_007, 64),
+                                 ((1 << 20) + 13, 64), ((1 << 20) + 13, 4096)])
+def test_chosen_splitters_match_oracle(pj, kind, n, k):
+    succ = W.random_list(n, 900 + n % 97 + k)
+    spl = _chosen(succ, kind, k, n + k)
+    want = oracle.list_rank(succ)
+    got, st = pj.list_rank(dev(succ), splitters=dev(spl), return_stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    assert st["sublists0"] == len(spl) + 1 + st["cuts0"]
+    if kind == "even" and k <= 1024:
+        # every sublist holds k nodes (the piece before the first chosen
+        # splitter starts at the head and holds fewer)
+        assert st["cuts0"] == 0 and st["max_sublist0"] == k
+    # in place, and with a status
+    d = dev(succ)
+    status = torch.full((1,), 9, dtype=torch.int32, device="cuda")
+    pj.list_rank(d, d, splitters=dev(spl), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == 0
+    assert np.array_equal(d.cpu().numpy(), want)
+
+
+def test_chosen_splitters_edge_cases(pj):
+    n = 50_000
+    succ, order = W.random_list_with_order(n, 77)
+    want = oracle.list_rank(succ)
+    cases = {
+        "head_only": order[:1],
+        "tail_only": order[-1:],
+        "every_node": np.random.default_rng(1).permutation(n).astype(np.int32),
+        "head_and_tail": order[[0, -1]],
+        "one_in_the_middle": order[n // 2:n // 2 + 1],   # long walks: cut at max_walk
+    }
+    for name, spl in cases.items():
+        got, st = pj.list_rank(dev(succ), splitters=dev(np.ascontiguousarray(spl)),
+                               max_walk=64, return_stats=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), want), name
+        assert st["max_sublist0"] <= 64, name
+    # small inputs still take the splitters (no one-workgroup shortcut)
+    for m in (1, 2, 3, 100):
+        s = W.random_list(m, m)
+        spl = np.arange(m, dtype=np.int32)[::2].copy()
+        got = pj.list_rank(dev(s), splitters=dev(spl))
+        torch.cuda.synchronize()
+        assert np.array_equal(got.cpu().numpy(), oracle.list_rank(s)), m
+
+
+def test_chosen_splitters_rejected_and_reported(pj):
+    n = 40_000
+    succ = W.random_list(n, 5)
+    status = torch.full((1,), 9, dtype=torch.int32, device="cuda")
+    dup = np.array([5, 17, 5, 900], np.int32)
+    pj.list_rank(dev(succ), splitters=dev(dup), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == pj.PJ_EINVAL
+    out_of_range = np.array([3, n + 2], np.int32)
+    pj.list_rank(dev(succ), splitters=dev(out_of_range), status=status)
+    torch.cuda.synchronize()
+    assert int(status.item()) == pj.PJ_EINVAL
+    spl = dev(np.array([1, 2], np.int32))
+    for kw in (dict(algo="wyllie"), dict(level0_state="separate")):
+        with pytest.raises(Exception):
+            pj.list_rank(dev(succ), splitters=spl, **kw)
+    with pytest.raises(Exception):
+        pj.list_rank_weighted(dev(succ), dev(np.ones(n, np.int32)), splitters=spl)
+    off = np.array([0, n], np.int64)
+    with pytest.raises(Exception):
+        pj.list_rank_batched(dev(succ), dev(off), h_offsets=off, splitters=spl)
+    # the input is a valid list: after the rejected calls a plain call is right
+    got = pj.list_rank(dev(succ))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.list_rank(succ))
+
+
+@pytest.mark.parametrize("layout", ["uniform", "sequential", "blocked"])
+@pytest.mark.parametrize("n", [20_000, 300_007, (1 << 22) + 5])
+def test_separate_state_matches_oracle(pj, layout, n):
+    if layout == "uniform":
+        succ = W.random_list(n, 61)
+    elif layout == "sequential":
+        succ = W.sequential_list(n)
+    else:
+        succ = W.blocked_list(n, 4096, 62)
+    want = oracle.list_rank(succ)
+    got = pj.list_rank(dev(succ), level0_state="separate")
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), want)
+    d = dev(succ)
+    pj.list_rank(d, d, level0_state="separate", to_tail=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(d.cpu().numpy(), n - 1 - want)
+
+
+def test_separate_state_batched_and_graph(pj):
+    succ, off = W.batched_lists(300, 4, 16, 63)
+    want = oracle.list_rank_batched(succ, off)[1]
+    d_succ, d_off = dev(succ), dev(off)
+    for use_graph in (False, True, True):
+        out = pj.list_rank_batched(d_succ, d_off, h_offsets=off, level0_state="separate",
+                                   use_graph=use_graph)
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), want), use_graph
+    # the same buffers with the packed state: a separate graph, same ranks
+    out = pj.list_rank_batched(d_succ, d_off, h_offsets=off, use_graph=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), want)
+    pj.graph_cache_clear()
+    with pytest.raises(Exception):
+        pj.list_rank(d_succ, level0_state=7)

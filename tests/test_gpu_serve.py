@@ -175,3 +175,72 @@ def test_sparse_graph_many_times(serve):
             st, _, out = srv.wait(rid, timeout_s=60)
             assert st == 0
             assert np.array_equal(out, want[j])
+
+
+def test_destroy_with_pending_requests_finishes_them(serve):
+    """Closing a server while more requests wait than its ticks can hold
+    returns, and every submitted request was solved before it did."""
+    reqs = make_mix(40, 13, lr_exp=(8, 16), cc_exp=(8, 13))
+    srv = serve.Server(hbm_budget=1 << 30, max_inflight=1, max_batch=2)
+    held = []
+    for r in reqs:
+        rid = submit(srv, r)
+        held.append((r, srv._live[rid][-1]))
+    done = threading.Event()
+
+    def closer():
+        srv.close()
+        done.set()
+
+    th = threading.Thread(target=closer, daemon=True)
+    th.start()
+    assert done.wait(120), "pj_server_destroy did not return"
+    for r, out in held:
+        out = out.numpy() if hasattr(out, "numpy") else out
+        assert np.array_equal(out, expected(r))
+
+
+def test_destroy_while_waiting_for_memory(serve):
+    """Destroy while the oldest request waits for budget held by a running
+    tick: the wait ends when the tick retires, not by spinning."""
+    reqs = [("lr", W.random_list(1 << 19, 700 + i)) for i in range(8)]
+    srv = serve.Server(hbm_budget=24 << 20, max_inflight=2, max_batch=64)
+    held = []
+    for r in reqs:
+        rid = submit(srv, r)
+        held.append((r, srv._live[rid][-1]))
+    done = threading.Event()
+    th = threading.Thread(target=lambda: (srv.close(), done.set()), daemon=True)
+    th.start()
+    assert done.wait(120), "pj_server_destroy did not return"
+    for r, out in held:
+        out = out.numpy() if hasattr(out, "numpy") else out
+        assert np.array_equal(out, expected(r))
+
+
+def test_large_requests_get_their_own_ticks(serve):
+    """Requests of at least large_items nodes (or vertices plus pairs) are
+    solved in ticks of their own, at most max_inflight - 1 at once; the small
+    ones keep flowing beside them, and every result is right."""
+    reqs = make_mix(60, 17, lr_exp=(6, 16), cc_exp=(6, 12))
+    big = [("lr", W.random_list(1 << 16, 9000 + i)) for i in range(5)]
+    big += [("cc", (*W.random_graph(1 << 13, 1 << 15, 9100 + i), 1 << 13)) for i in range(3)]
+    mixed = []
+    for i, r in enumerate(reqs):
+        mixed.append(r)
+        if i % 8 == 3 and big:
+            mixed.append(big.pop())
+    mixed += big
+    items = [len(d) if k == "lr" else d[2] + len(d[0]) for k, d in mixed]
+    large = 1 << 15
+    with serve.Server(hbm_budget=2 << 30, max_inflight=3, max_batch=16, large_items=large) as srv:
+        ids = [submit(srv, r) for r in mixed]
+        for rid, r in zip(ids, mixed):
+            st, _, out = srv.wait(rid, timeout_s=60)
+            assert st == 0
+            assert np.array_equal(out, expected(r))
+        s = srv.stats()
+    n_large = sum(1 for it in items if it >= large)
+    assert n_large >= 8
+    assert s["large_ticks"] == n_large
+    assert s["completed"] == len(mixed)
