@@ -20,6 +20,9 @@ CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(PKG, "libptrjump.so")
+# measurement probe for the benchmark (not part of the solver library)
+PROBE_SRC = os.path.join(PKG, "probe", "chase.hip")
+PROBE_LIB = os.path.join(PKG, "libpjprobe.so")
 ARCH = os.environ.get("PJ_OFFLOAD_ARCH", "gfx950")
 
 
@@ -72,7 +75,20 @@ def build(verbose=False, jobs=None):
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
     os.replace(tmp, LIB)
+    build_probe(verbose)
     return LIB
+
+
+def build_probe(verbose=False):
+    tmp = PROBE_LIB + ".tmp"
+    cmd = [_hipcc(), *COMMON, "-shared", PROBE_SRC, "-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"probe build failed:\n{r.stdout}\n{r.stderr}")
+    os.replace(tmp, PROBE_LIB)
+    return PROBE_LIB
 
 
 if __name__ == "__main__":
