@@ -446,9 +446,12 @@ def run_extras(torch, pj, dev, d_succ, d_rank, d_order, n, args):
     log(f"wyllie uniform {ms:.3f} ms")
 
     # weighted ranks on the same list (separate state, weights beside succ);
-    # closed form: the exclusive prefix of the weights along the list order
+    # closed form: the exclusive prefix of the weights along the list order.
+    # The library's sums are int32, so the weights are drawn small enough
+    # that the list's total fits (below 16 per node: under 2^30 at 2^26)
     wts = torch.from_numpy(np.random.default_rng(W.SEED_BASE + 7).integers(
-        0, 100, n).astype(np.int32)).to(dev)
+        0, 16, n).astype(np.int32)).to(dev)
+    assert 15 * n < 2**31
     ms = timed(torch, lambda: pj.list_rank_weighted(d_succ, wts, d_rank), steps, 1)
     wo = wts[d_order].to(torch.int64)
     ok = require(bool(torch.equal(d_rank[d_order].to(torch.int64), torch.cumsum(wo, 0) - wo)),
