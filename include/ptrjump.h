@@ -57,6 +57,7 @@ typedef struct ihipStream_t *pj_stream_t;
 #define PJ_ENOTFOUND (-7) /* serving: unknown request id */
 #define PJ_EBUSY (-8)     /* serving: request not finished yet (poll again) */
 #define PJ_ESHUTDOWN (-9) /* serving: server is shutting down */
+#define PJ_ESCRATCH (-10) /* pj_list_rank_noalloc: the input needs more than its fixed scratch */
 
 /* ------------------------------------------------------------- algorithms */
 #define PJ_ALGO_AUTO 0        /* tuned choice (ruling set for lists, SV for components) */
@@ -180,6 +181,28 @@ int pj_list_rank_batched_ex(const int32_t *succ, const int64_t *offsets, int64_t
 /* Bytes of workspace a call with these sizes needs (L = 1: enough for both the
  * plain call and a batched call holding one list). */
 size_t pj_list_rank_workspace_bytes(int64_t total_nodes, int64_t L, const pj_opts *opts);
+
+/*
+ * List ranking that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, results and in-place
+ * rule as pj_list_rank_ex; the workspace comes from one fixed device array
+ * of pj_list_rank_noalloc_max_bytes() bytes (64 MiB) that the library holds
+ * on every device it runs on until the process ends.  An input whose
+ * workspace (pj_list_rank_workspace_bytes with the same options) exceeds
+ * that size is refused with PJ_ESCRATCH before anything is enqueued: with
+ * the default options that admits lists of up to about 2^24 nodes.
+ * opts->workspace, opts->use_graph, opts->stats and validate without
+ * d_status are PJ_EINVAL (they allocate or read back through host memory).
+ * The call makes no hipMalloc, hipMallocAsync, hipFree or hipHostMalloc.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (on different streams, or from different threads without
+ * ordering) race and give unspecified ranks; calls ordered on one stream are
+ * safe.
+ */
+int pj_list_rank_noalloc(const int32_t *succ, int64_t n, int32_t *rank, const pj_opts *opts,
+                         pj_stream_t stream);
+size_t pj_list_rank_noalloc_max_bytes(void);
 
 /*
  * Weighted list ranking: the problem the ruling set solves on its splitter

@@ -10,6 +10,7 @@ __all__ = [
     "load",
     "list_rank",
     "list_rank_batched",
+    "list_rank_noalloc",
     "list_rank_weighted",
     "list_rank_weighted_batched",
     "connected_components",
@@ -21,7 +22,7 @@ __all__ = [
 def __getattr__(name):
     # torch is imported lazily so that loading the C library (e.g. to list its
     # symbols on a machine without a GPU) does not need it
-    if name in ("list_rank", "list_rank_batched", "list_rank_weighted",
+    if name in ("list_rank", "list_rank_batched", "list_rank_noalloc", "list_rank_weighted",
                 "list_rank_weighted_batched", "connected_components",
                 "connected_components_batched", "make_opts", "tune_list_rank", "tune_lookup",
                 "tune_save", "tune_load", "tune_clear", "graph_cache_clear"):

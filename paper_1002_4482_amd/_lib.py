@@ -23,6 +23,7 @@ PJ_EBUDGET = -6
 PJ_ENOTFOUND = -7
 PJ_EBUSY = -8
 PJ_ESHUTDOWN = -9
+PJ_ESCRATCH = -10
 
 ALGO = {"auto": 0, "wyllie": 1, "ruling_set": 2, "sv": 3}
 LEVEL0_STATE = {"auto": 0, "separate": 1}
@@ -150,6 +151,8 @@ SIGNATURES = [
     ("pj_list_rank_batched", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP]),
     ("pj_list_rank_batched_ex", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _VP]),
     ("pj_list_rank_workspace_bytes", _SZ, [_I64, _I64, _VP]),
+    ("pj_list_rank_noalloc", ctypes.c_int, [_VP, _I64, _VP, _VP, _VP]),
+    ("pj_list_rank_noalloc_max_bytes", _SZ, []),
     ("pj_list_rank_weighted", ctypes.c_int, [_VP, _VP, _I64, _VP, _VP, _VP]),
     ("pj_list_rank_weighted_batched", ctypes.c_int, [_VP, _VP, _VP, _I64, _VP, _VP, _VP]),
     ("pj_list_rank_weighted_workspace_bytes", _SZ, [_I64, _I64, _VP]),

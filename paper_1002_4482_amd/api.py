@@ -116,6 +116,27 @@ def list_rank(succ, rank=None, *, stream=None, return_stats=False, **kw):
     return (rank, st.to_dict()) if return_stats else rank
 
 
+def list_rank_noalloc(succ, rank=None, *, stream=None, **kw):
+    """pj_list_rank_noalloc: the same ranks as list_rank, with the workspace
+    taken from the library's fixed device scratch (no device allocation in
+    the call; `rank` is allocated here by torch when not given)."""
+    succ = _dev_i32(succ, "succ")
+    n = succ.numel()
+    if rank is None:
+        rank = torch.empty_like(succ)
+    _dev_i32(rank, "rank")
+    _need(rank, n, "rank")
+    o = make_opts(**kw)
+    rc = _lib.load().pj_list_rank_noalloc(_ptr(succ), n, _ptr(rank), ctypes.byref(o),
+                                          _stream_ptr(stream))
+    _check(rc, "pj_list_rank_noalloc")
+    return rank
+
+
+def list_rank_noalloc_max_bytes():
+    return int(_lib.load().pj_list_rank_noalloc_max_bytes())
+
+
 def list_rank_batched(succ, offsets, rank=None, *, h_offsets=None, stream=None,
                       return_stats=False, **kw):
     """Rank L lists concatenated in `succ` (local ids) with device int64

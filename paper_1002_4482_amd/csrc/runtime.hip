@@ -221,6 +221,7 @@ const char* pj_strerror(int code) {
     case PJ_ENOTFOUND: return "unknown request id";
     case PJ_EBUSY: return "request not finished";
     case PJ_ESHUTDOWN: return "server shutting down";
+    case PJ_ESCRATCH: return "input needs more workspace than the no-allocation scratch holds";
     default: return "unknown status";
   }
 }

@@ -145,3 +145,26 @@ def test_argument_checks_before_any_device_work(lib):
     # weighted workspace is larger than the packed form's
     assert (L.pj_list_rank_weighted_workspace_bytes(1 << 20, 1, None)
             > L.pj_list_rank_workspace_bytes(1 << 20, 1, None))
+
+
+def test_noalloc_refusals_before_any_device_work(lib):
+    """pj_list_rank_noalloc refuses, on the host and before any HIP call, an
+    input whose workspace exceeds its fixed scratch, and the options that
+    would allocate or read back through host memory."""
+    from paper_1002_4482_amd import _lib
+    L = _lib.load()
+    buf = np.zeros(64, dtype=np.int32)
+    p = buf.ctypes.data
+    assert L.pj_list_rank_noalloc_max_bytes() == 64 << 20
+    assert L.pj_list_rank_workspace_bytes(1 << 24, 1, None) <= L.pj_list_rank_noalloc_max_bytes()
+    assert L.pj_list_rank_noalloc(p, 1 << 25, p, None, None) == _lib.PJ_ESCRATCH
+    assert L.pj_list_rank_noalloc(p, -1, p, None, None) == _lib.PJ_EINVAL
+    assert L.pj_strerror(_lib.PJ_ESCRATCH).startswith(b"input needs more workspace")
+    st = _lib.PjStats()
+    for field, value in (("use_graph", 1), ("validate", 1), ("workspace", p),
+                         ("stats", ctypes.pointer(st))):
+        o = _lib.PjOpts()
+        L.pj_opts_init(ctypes.byref(o))
+        setattr(o, field, value)
+        assert L.pj_list_rank_noalloc(p, 16, p + 4 * 32, ctypes.byref(o), None) == \
+            _lib.PJ_EINVAL, field
