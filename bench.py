@@ -356,15 +356,17 @@ def single_workload(torch, pj, dev, args):
     elif wl.startswith("list_"):
         n = 1 << (20 if wl == "list_uniform_2p20" else args.log2n)
         if wl == "list_sequential":
-            s = W.sequential_list(n)
+            s, order = W.sequential_list(n), np.arange(n)
         elif wl == "list_blocked":
-            s = W.blocked_list(n, 4096, W.SEED_BASE + 2)
+            s, order = W.blocked_list_with_order(n, 4096, W.SEED_BASE + 2)
         else:
-            s = W.random_list(n, W.SEED_BASE + (1 if wl == "list_uniform_2p20" else 2))
+            s, order = W.random_list_with_order(
+                n, W.SEED_BASE + (1 if wl == "list_uniform_2p20" else 2))
         algo = "wyllie" if wl == "list_uniform_wyllie" else "ruling_set"
         ds = torch.from_numpy(s).to(dev)
         dr = torch.empty_like(ds)
         ms = timed(torch, lambda: pj.list_rank(ds, dr, algo=algo), args.steps, args.warmup)
+        require(closed_form_ok(torch, dr, torch.from_numpy(order).to(dev).long()), wl)
         _, st = pj.list_rank(ds, dr, algo=algo, return_stats=True)
         rec.update(n=n, algo=algo, ms=round(ms, 4), nodes_per_s=round(n / (ms * 1e-3), 1),
                    phases=st["phases"], levels=st["levels"], level_nodes=st["level_nodes"])
@@ -378,6 +380,9 @@ def single_workload(torch, pj, dev, args):
         lab = torch.empty(nv, dtype=torch.int32, device=dev)
         ms = timed(torch, lambda: pj.connected_components(ds, dd, nv, lab), args.steps,
                    args.warmup)
+        import oracle
+        require(np.array_equal(lab.cpu().numpy(), oracle.connected_components(src, dst, nv)),
+                wl)
         _, st = pj.connected_components(ds, dd, nv, lab, return_stats=True)
         rec.update(n=nv, m=m, ms=round(ms, 4), edges_per_s=round(m / (ms * 1e-3), 1),
                    rounds=st["rounds"], phases=st["phases"])
@@ -387,6 +392,8 @@ def single_workload(torch, pj, dev, args):
         dbr = torch.empty_like(dbs)
         ms = timed(torch, lambda: pj.list_rank_batched(dbs, dboff, dbr, h_offsets=boff),
                    args.steps, args.warmup)
+        import oracle
+        require(np.array_equal(dbr.cpu().numpy(), oracle.list_rank_batched(bs, boff)[1]), wl)
         _, st = pj.list_rank_batched(dbs, dboff, dbr, h_offsets=boff, return_stats=True)
         rec.update(total_nodes=int(boff[-1]), ms=round(ms, 4),
                    nodes_per_s=round(int(boff[-1]) / (ms * 1e-3), 1), phases=st["phases"],

@@ -164,7 +164,10 @@ int pj_list_rank_ex(const int32_t *succ, int64_t n, int32_t *rank, const pj_opts
                     pj_stream_t stream);
 
 /*
- * Batched list ranking: L independent lists concatenated.  offsets is a
+ * Batched list ranking: L independent lists concatenated, each ranked as in
+ * the problem statement of Section 3 (the ruling set of Section 3.2 ranks
+ * the whole batch as one forest, with a splitter at every list head, as its
+ * recursion already does for the splitter list).  offsets is a
  * DEVICE int64[L+1] table (offsets[0] == 0, non-decreasing); list l occupies
  * [offsets[l], offsets[l+1]) and its successors are LOCAL ids in
  * [0, size_l) (tail -1 or self).  rank receives local ranks per list.  With
@@ -287,7 +290,9 @@ int pj_connected_components_ex(const int32_t *src, const int32_t *dst, int64_t n
                                int32_t *label, const pj_opts *opts, pj_stream_t stream);
 
 /*
- * Batched components: G independent graphs.  vtx_off and edge_off are DEVICE
+ * Batched components: G independent graphs, each solved as in the problem
+ * statement of Section 4 (the batch is one disjoint union of the graphs,
+ * solved by one Shiloach-Vishkin run).  vtx_off and edge_off are DEVICE
  * int64[G+1] tables; graph g owns vertices [vtx_off[g], vtx_off[g+1]) and
  * pairs [edge_off[g], edge_off[g+1]), with LOCAL vertex ids.  label receives
  * local labels (smallest local id of each component).

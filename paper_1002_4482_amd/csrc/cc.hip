@@ -26,7 +26,8 @@
 // Before step 2 a compaction kernel replaces every pair by the pair of its
 // ends' parents and drops it when the two agree (see sv_compact); steps 2
 // and 3 read the survivors.  Round 1 starts from D = identity, skips 1a,
-// and does steps 2 and 3 inside its compaction (see sv_compact).
+// and does steps 2 and 3 by sorting the input pairs by slice and hooking
+// them (see sv_bucket and sv_hook_first).
 // Concurrent writes to one root land in arbitrary order; every outcome is
 // one the arbitrary-CRCW algorithm allows: step 2 only hooks star roots onto
 // strictly smaller ids, step 3 only hooks stars that no step-2 hook touched,
@@ -154,141 +155,309 @@ __global__ void __launch_bounds__(256) sv_mark(const int32_t* __restrict__ D,
   raise_flag(&w[s], changed);
 }
 
-// Pair compaction, a kernel of its own between steps 1b and 2.  A stored
-// pair (x, y) stands for an input pair (i, j) with x in i's tree and y in j's
-// tree; it is replaced by (D[x], D[y]).  Parents lie in the same trees, so
-// the connectivity the pair carries is unchanged, and after round 1 the
-// stored ends are roots or near-roots: a shrinking set of words that stays
-// in cache, instead of gathers over the whole parent array every round.
-// Pairs whose two parents agree lie inside one tree for good (trees only
-// merge) and are dropped.  The survivors are exactly the parents steps 2 and
-// 3 need.  After round 1, D is not written while this kernel runs: step 2
-// may hook one root twice (arbitrary winner), and a drop decided between two
-// such writes could rest on a parent the second write replaces.  A workgroup
-// reserves room for the survivors of each chunk of kCompactPer * 256 pairs
-// with one atomic.
-//
-// Round 1 (kFirst) is this kernel alone.  Every vertex is its own parent,
-// so the input pairs are range-checked and copied without reading D; and
-// every vertex is the root of a star, so step 2 has every pair (a > b) hook
-// D[a] = b (concurrent writes, arbitrary winner) and stamp Q[b].  Then every
-// vertex with a pair is hooked (the larger end of one) or stamped (the
-// smaller end), step 3 finds no stagnant root, and the stamps are never read:
-// the kernel only stores the hooks.  These are plain stores, unlike the
-// hooks of later rounds: nothing reads D in this kernel, and round 1 keeps
-// every pair, so a hook lost between two XCDs' caches would only leave its
-// vertex a root for round 2 to hook (measured: 3% faster than write-through
-// stores, no wrong label under stress).
+// ------------------------------------------------ XCD-local pair layout
+// The parent array of a large graph (16 MiB at 2^22 vertices) is four
+// times one XCD's L2, so a gather or store at a random vertex misses that
+// L2 most of the time, and round 1's 2^25 random hook stores dirty partial
+// lines.  The vertices are therefore dealt into kSlices slices, one per XCD,
+// by blocks of 2^sshift consecutive ids (slice_of), and round 1 first sorts
+// every chunk of input pairs by the slice of the end it will hook
+// (sv_bucket).  Workgroups
+// are dispatched round-robin over the XCDs, so the workgroups of one XCD
+// (blockIdx.x % kSlices) take the runs of one slice: round 1's hooks
+// (sv_hook_first) then store into, and round 2's compaction gathers one end
+// from, an eighth of D that stays in that XCD's L2.  Nothing depends on the
+// mapping for correctness, only the hit rate.  Dealing blocks round-robin,
+// not one contiguous id range per slice, keeps the slices equally loaded
+// when pair ends are not uniform over the ids (the larger end of a uniform
+// pair is not).  Blocks are 4 KiB of D (2^10 ids; fewer for small graphs,
+// so that every slice holds at least 32 blocks): on the 2^22-vertex graph,
+// measured, 2.61 ms per solve against 2.76 ms with 128-byte blocks and
+// 2.98 ms with 64 KiB blocks.
+constexpr int kSlices = 8;
+constexpr int kSliceShiftMax = 10;
 constexpr int kCompactPer = 8;
 constexpr int kCompactWaves = 256 / kWave;
-// After round 1 a workgroup also drops repeats within its chunk: contracted
-// pairs pile up on the few roots that remain late in a solve (thousands of
-// copies of one pair of roots), and a copy joins nothing the first does not.
-// Open addressing in LDS, pairs ordered (min, max); a pair that finds no free
+constexpr int kBucketChunk = 256 * kCompactPer;  // pairs per sorted chunk
+constexpr int kSegStride = kSlices + 1;
+constexpr int kGroupChunks = 8;                  // chunks per unit of work
+
+__device__ __forceinline__ int slice_of(int v, int sshift) { return (v >> sshift) & (kSlices - 1); }
+
+// Slice block size for n vertices: 2^10 ids, or fewer so that each slice
+// gets at least 32 blocks (never below one 128-byte line).
+inline int slice_shift(int64_t n) {
+  int lg = 0;
+  while ((int64_t(1) << lg) < n) ++lg;
+  return std::max(5, std::min(kSliceShiftMax, lg - 8));
+}
+
+__device__ __forceinline__ int wave_incl_scan(int v) {
+  const int lane = lane_id();
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int u = __shfl_up(v, o, kWave);
+    if (lane >= o) v += u;
+  }
+  return v;
+}
+
+// Round 1, first pass.  Every pair is range-checked, self-loops are dropped,
+// and each kept pair is oriented (a, b) with a > b (the hook D[a] = b of
+// round 1) and written back inside its own chunk of kBucketChunk positions,
+// sorted by slice_of(a).  seg[c * kSegStride + q] is where slice q's run
+// starts inside chunk c, seg[c * kSegStride + kSlices] the chunk's kept
+// pairs.  The order inside a run is the input order, wave by wave.
+__global__ void __launch_bounds__(256) sv_bucket(const int32_t* __restrict__ src,
+                                                 const int32_t* __restrict__ dst, int64_t m,
+                                                 int n, int sshift, int2* __restrict__ pout,
+                                                 int32_t* __restrict__ seg, int32_t* w,
+                                                 CcCtl* ctl) {
+  // (slice, item, wave) counts, slice-major, then their exclusive prefix
+  __shared__ int cnt[kSlices * kCompactPer * kCompactWaves];
+  __shared__ int wsum[kCompactWaves];
+  static_assert(kSlices * kCompactPer * kCompactWaves == 256, "one count per thread");
+  const int wave = threadIdx.x / kWave;
+  const int lane = lane_id();
+  const int64_t nchunks = (m + kBucketChunk - 1) / kBucketChunk;
+  bool bad = false, any = false;
+  for (int64_t c = blockIdx.x; c < nchunks; c += gridDim.x) {
+    const int64_t c0 = c * kBucketChunk;
+    int a[kCompactPer], b[kCompactPer], q[kCompactPer], rk[kCompactPer];
+#pragma unroll
+    for (int t = 0; t < kCompactPer; ++t) {
+      const int64_t e = c0 + t * 256 + threadIdx.x;
+      a[t] = b[t] = 0;
+      q[t] = -1;
+      if (e < m) {
+        const int u = src[e], v = dst[e];
+        if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) {
+          bad = true;
+        } else if (u != v) {
+          a[t] = u > v ? u : v;
+          b[t] = u > v ? v : u;
+          q[t] = slice_of(a[t], sshift);
+        }
+      }
+    }
+#pragma unroll
+    for (int t = 0; t < kCompactPer; ++t) {
+      rk[t] = 0;
+#pragma unroll
+      for (int k = 0; k < kSlices; ++k) {
+        const uint64_t mk = __ballot(q[t] == k);
+        if (q[t] == k) rk[t] = lanes_below(mk);
+        if (lane == 0) cnt[(k * kCompactPer + t) * kCompactWaves + wave] = __popcll(mk);
+      }
+    }
+    __syncthreads();
+    const int mine = cnt[threadIdx.x];
+    const int incl = wave_incl_scan(mine);
+    if (lane == kWave - 1) wsum[wave] = incl;
+    __syncthreads();
+    int excl = incl - mine;
+    for (int i = 0; i < wave; ++i) excl += wsum[i];
+    cnt[threadIdx.x] = excl;  // each thread rewrites only the entry it read
+    if (threadIdx.x % (kCompactPer * kCompactWaves) == 0)
+      seg[c * kSegStride + threadIdx.x / (kCompactPer * kCompactWaves)] = excl;
+    if (threadIdx.x == 255) seg[c * kSegStride + kSlices] = excl + mine;
+    __syncthreads();
+#pragma unroll
+    for (int t = 0; t < kCompactPer; ++t)
+      if (q[t] >= 0) {
+        pout[c0 + cnt[(q[t] * kCompactPer + t) * kCompactWaves + wave] + rk[t]] =
+            make_int2(a[t], b[t]);
+        any = true;
+      }
+    __syncthreads();  // cnt and wsum are reused by the next chunk
+  }
+  if (__ballot(bad) && lane == 0) atomicOr(&ctl->err, kErrRange);
+  raise_flag(&w[1], any);
+}
+
+// One unit of work of the slice-sorted pairs: slice q's runs in the
+// kGroupChunks chunks of group g, as a flat range [0, pre[kGroupChunks]);
+// flat item f lies in chunk j with pre[j] <= f < pre[j + 1], at position
+// start[j] + f - pre[j].  Called by every thread; ends with a barrier.
+__device__ __forceinline__ void load_unit(const int32_t* __restrict__ seg, int64_t nchunks,
+                                          int64_t g, int q, int* pre, int64_t* start) {
+  if (threadIdx.x < kGroupChunks) {
+    const int64_t c = g * kGroupChunks + threadIdx.x;
+    int len = 0;
+    int64_t st = 0;
+    if (c < nchunks) {
+      const int lo = seg[c * kSegStride + q];
+      len = seg[c * kSegStride + q + 1] - lo;
+      st = c * kBucketChunk + lo;
+    }
+    start[threadIdx.x] = st;
+    pre[threadIdx.x + 1] = len;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pre[0] = 0;
+    for (int j = 1; j <= kGroupChunks; ++j) pre[j] += pre[j - 1];
+  }
+  __syncthreads();
+}
+
+__device__ __forceinline__ int64_t unit_pos(const int* pre, const int64_t* start, int f) {
+  int j = 0;
+  while (pre[j + 1] <= f) ++j;  // f < pre[kGroupChunks], so j < kGroupChunks
+  return start[j] + (f - pre[j]);
+}
+
+// Round 1, second pass: step 2 with every vertex the root of a star.  Each
+// kept pair (a, b), a > b, hooks D[a] = b (concurrent writes to one a land
+// in arbitrary order).  Every vertex with a pair is then hooked (the larger
+// end of one) or hooked onto (the smaller end), so step 3 finds no stagnant
+// root and the stamps of step 2 are never read: only the hooks are stored.
+// The workgroups of slice q store only into slice q's lines.  Plain stores:
+// D is not read in this kernel (the memory-model argument for them is given
+// with the library's design notes on store discipline).
+constexpr int kHookFirstPer = 12;
+
+__global__ void __launch_bounds__(256) sv_hook_first(const int2* __restrict__ pairs,
+                                                     const int32_t* __restrict__ seg,
+                                                     int64_t nchunks, int32_t* __restrict__ D) {
+  __shared__ int pre[kGroupChunks + 1];
+  __shared__ int64_t start[kGroupChunks];
+  const int q = blockIdx.x % kSlices;
+  const int64_t ngroups = (nchunks + kGroupChunks - 1) / kGroupChunks;
+  for (int64_t g = blockIdx.x / kSlices; g < ngroups; g += gridDim.x / kSlices) {
+    load_unit(seg, nchunks, g, q, pre, start);
+    const int total = pre[kGroupChunks];
+    for (int f0 = 0; f0 < total; f0 += 256 * kHookFirstPer) {
+      int2 p[kHookFirstPer];
+#pragma unroll
+      for (int t = 0; t < kHookFirstPer; ++t) {
+        const int f = f0 + t * 256 + threadIdx.x;
+        p[t] = f < total ? pairs[unit_pos(pre, start, f)] : make_int2(-1, 0);
+      }
+#pragma unroll
+      for (int t = 0; t < kHookFirstPer; ++t)
+        if (p[t].x >= 0) D[p[t].x] = p[t].y;
+    }
+    __syncthreads();  // pre and start are reused by the next unit
+  }
+}
+
+// Pair compaction, a kernel of its own between steps 1b and 2 (rounds 2 and
+// later).  A stored pair (x, y) stands for an input pair (i, j) with x in
+// i's tree and y in j's tree; it is replaced by (D[x], D[y]).  Parents lie
+// in the same trees, so the connectivity the pair carries is unchanged, and
+// after round 2 the stored ends are roots or near-roots: a shrinking set of
+// words that stays in cache, instead of gathers over the whole parent array
+// every round.  Pairs whose two parents agree lie inside one tree for good
+// (trees only merge) and are dropped.  The survivors are exactly the parents
+// steps 2 and 3 need.  D is not written while this kernel runs: step 2 may
+// hook one root twice (arbitrary winner), and a drop decided between two
+// such writes could rest on a parent the second write replaces.  A
+// workgroup reserves room for the survivors of each chunk of kCompactPer *
+// 256 pairs with one atomic.
+//
+// kSorted (round 2) reads round 1's slice-sorted pairs unit by unit, the
+// workgroups of slice q taking slice q's runs, so one of the two gathers
+// stays in the XCD's L2; later rounds read the dense survivors.
+//
+// A workgroup also drops repeats within its chunk: contracted pairs pile up
+// on the few roots that remain late in a solve (thousands of copies of one
+// pair of roots), and a copy joins nothing the first does not.  Open
+// addressing in LDS, pairs ordered (min, max); a pair that finds no free
 // slot within kDedupProbes is kept.
 constexpr int kDedupSlots = 4096;  // >= 2 * 256 * kCompactPer
 constexpr int kDedupProbes = 8;
 constexpr unsigned long long kDedupEmpty = ~0ull;
 
-template <bool kFirst>
-__global__ void __launch_bounds__(256) sv_compact(const int32_t* __restrict__ src,
-                                                  const int32_t* __restrict__ dst,
-                                                  const int2* __restrict__ pin, int64_t m_host,
+template <bool kSorted>
+__global__ void __launch_bounds__(256) sv_compact(const int2* __restrict__ pin,
                                                   const unsigned long long* m_dev,
-                                                  int32_t* __restrict__ D, int n,
+                                                  const int32_t* __restrict__ seg,
+                                                  int64_t nchunks, int32_t* __restrict__ D,
                                                   int2* __restrict__ pout,
-                                                  unsigned long long* m_out, int32_t* w, int s,
-                                                  CcCtl* ctl) {
+                                                  unsigned long long* m_out, int32_t* w,
+                                                  int s) {
   if (converged(w, s)) return;
-  const int64_t m = kFirst ? m_host : (int64_t)*m_dev;
   __shared__ int cnt[kCompactPer][kCompactWaves];
   __shared__ unsigned long long chunk_base;
-  __shared__ unsigned long long seen[kFirst ? 1 : kDedupSlots];
-  bool hooked = false;
+  __shared__ unsigned long long seen[kDedupSlots];
+  __shared__ int pre[kGroupChunks + 1];
+  __shared__ int64_t start[kGroupChunks];
   const int wave = threadIdx.x / kWave;
-  const int64_t chunk = 256 * kCompactPer;
-  bool bad = false;
-  for (int64_t c0 = (int64_t)blockIdx.x * chunk; c0 < m; c0 += (int64_t)gridDim.x * chunk) {
-    if (!kFirst) {
+  const int64_t m = kSorted ? 0 : (int64_t)*m_dev;
+  const int q = blockIdx.x % kSlices;
+  const int64_t nunits = kSorted ? (nchunks + kGroupChunks - 1) / kGroupChunks
+                                 : (m + kBucketChunk - 1) / kBucketChunk;
+  const int64_t ustep = kSorted ? gridDim.x / kSlices : gridDim.x;
+  for (int64_t u = kSorted ? blockIdx.x / kSlices : blockIdx.x; u < nunits; u += ustep) {
+    int total;
+    if (kSorted) {
+      load_unit(seg, nchunks, u, q, pre, start);
+      total = pre[kGroupChunks];
+    } else {
+      total = (int)min((int64_t)kBucketChunk, m - u * kBucketChunk);
+    }
+    for (int f0 = 0; f0 < total; f0 += kBucketChunk) {
       for (int i = threadIdx.x; i < kDedupSlots; i += 256) seen[i] = kDedupEmpty;
       __syncthreads();
-    }
-    int du[kCompactPer], dv[kCompactPer];
-    bool keep[kCompactPer];
+      int du[kCompactPer], dv[kCompactPer];
+      bool keep[kCompactPer];
 #pragma unroll
-    for (int t = 0; t < kCompactPer; ++t) {
-      const int64_t e = c0 + t * 256 + threadIdx.x;
-      keep[t] = false;
-      du[t] = dv[t] = 0;
-      if (e < m) {
-        if (kFirst) {
-          const int u = src[e], v = dst[e];
-          if ((unsigned)u >= (unsigned)n || (unsigned)v >= (unsigned)n) {
-            bad = true;
-          } else {
-            du[t] = u;
-            dv[t] = v;
-            keep[t] = u != v;
-            if (keep[t]) {
-              const int a = u > v ? u : v;
-              D[a] = u > v ? v : u;
-              hooked = true;
-            }
-          }
-        } else {
-          const int2 p = pin[e];
+      for (int t = 0; t < kCompactPer; ++t) {
+        const int f = f0 + t * 256 + threadIdx.x;
+        keep[t] = false;
+        du[t] = dv[t] = 0;
+        if (f < total) {
+          const int2 p = pin[kSorted ? unit_pos(pre, start, f) : u * kBucketChunk + f];
           const int x = D[p.x], y = D[p.y];
           du[t] = x < y ? x : y;
           dv[t] = x < y ? y : x;
           keep[t] = x != y;
         }
       }
-    }
-    if (!kFirst) {
 #pragma unroll
       for (int t = 0; t < kCompactPer; ++t) {
         if (!keep[t]) continue;
-        const unsigned long long key = ((unsigned long long)(unsigned)du[t] << 32) | (unsigned)dv[t];
+        const unsigned long long key =
+            ((unsigned long long)(unsigned)du[t] << 32) | (unsigned)dv[t];
         unsigned h = mix32((unsigned)du[t] * 0x9E3779B1u ^ (unsigned)dv[t]);
-        for (int q = 0; q < kDedupProbes; ++q, ++h) {
-          const unsigned long long old = atomicCAS(&seen[h & (kDedupSlots - 1)], kDedupEmpty, key);
-          if (old == kDedupEmpty) break;             // first copy in this chunk
-          if (old == key) {                          // a repeat
+        for (int pr = 0; pr < kDedupProbes; ++pr, ++h) {
+          const unsigned long long old =
+              atomicCAS(&seen[h & (kDedupSlots - 1)], kDedupEmpty, key);
+          if (old == kDedupEmpty) break;  // first copy in this chunk
+          if (old == key) {               // a repeat
             keep[t] = false;
             break;
           }
         }
       }
-    }
 #pragma unroll
-    for (int t = 0; t < kCompactPer; ++t) {
-      const uint64_t bm = __ballot(keep[t]);
-      if (lane_id() == 0) cnt[t][wave] = __popcll(bm);
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int total = 0;
-      for (int t = 0; t < kCompactPer; ++t)
-        for (int q = 0; q < kCompactWaves; ++q) {
-          const int c = cnt[t][q];
-          cnt[t][q] = total;
-          total += c;
-        }
-      chunk_base = total ? atomicAdd(m_out, (unsigned long long)total) : 0ull;
-    }
-    __syncthreads();
-    const unsigned long long cb = chunk_base;
+      for (int t = 0; t < kCompactPer; ++t) {
+        const uint64_t bm = __ballot(keep[t]);
+        if (lane_id() == 0) cnt[t][wave] = __popcll(bm);
+      }
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int t = 0; t < kCompactPer; ++t)
+          for (int k = 0; k < kCompactWaves; ++k) {
+            const int c = cnt[t][k];
+            cnt[t][k] = acc;
+            acc += c;
+          }
+        chunk_base = acc ? atomicAdd(m_out, (unsigned long long)acc) : 0ull;
+      }
+      __syncthreads();
+      const unsigned long long cb = chunk_base;
 #pragma unroll
-    for (int t = 0; t < kCompactPer; ++t) {
-      const uint64_t bm = __ballot(keep[t]);
-      if (keep[t]) pout[cb + cnt[t][wave] + lanes_below(bm)] = make_int2(du[t], dv[t]);
+      for (int t = 0; t < kCompactPer; ++t) {
+        const uint64_t bm = __ballot(keep[t]);
+        if (keep[t]) pout[cb + cnt[t][wave] + lanes_below(bm)] = make_int2(du[t], dv[t]);
+      }
+      __syncthreads();
     }
-    __syncthreads();
   }
-  if (kFirst && __ballot(bad) && lane_id() == 0) atomicOr(&ctl->err, kErrRange);
-  if (kFirst) raise_flag(&w[s], hooked);
 }
-
 // Pair kernels take kPairsPer pairs per thread per iteration, issuing all
 // their loads before using any, so that enough gathers are in flight.
 constexpr int kPairsPer = 8;
@@ -571,6 +740,7 @@ struct CcBuffers {
   int32_t* gdst = nullptr;
   int32_t* gerr = nullptr;               // batched: per-graph out-of-range flag
   int2* pairs[2] = {};                   // surviving parent pairs (ping-pong)
+  int32_t* seg = nullptr;                // round 1: slice runs of each sorted chunk
   int32_t* status_tmp = nullptr;
 };
 
@@ -593,6 +763,7 @@ size_t cc_carve(int64_t n, int64_t m, int64_t G, bool batched, bool want_status,
   const size_t mm = (size_t)std::max<int64_t>(m, 1);
   take(b->pairs[0], mm);
   take(b->pairs[1], mm);
+  take(b->seg, (size_t)std::max<int64_t>((m + kBucketChunk - 1) / kBucketChunk, 1) * kSegStride);
   if (batched) {
     take(b->gsrc, (size_t)std::max<int64_t>(m, 1));
     take(b->gdst, (size_t)std::max<int64_t>(m, 1));
@@ -618,6 +789,9 @@ struct CcRun {
   int32_t* status = nullptr;
   int max_rounds = 0, wlen = 0;
   int ni = 0, gv = 1, gp = 1, gh = 1, gcap = 1;
+  int gq = kSlices;        // grids over slice-sorted units: a multiple of kSlices
+  int sshift = 5;          // slice block: 2^sshift ids
+  int64_t nchunks = 0;     // sorted chunks of round 1
   CcBuffers b;
   hipStream_t stream = nullptr;
   PhaseTimer* tm = nullptr;
@@ -643,6 +817,11 @@ void cc_setup(CcRun& r, const int32_t* src, const int32_t* dst, int64_t n, int64
   r.gv = grid_for(n, 256, r.gcap);
   r.gp = grid_for((m + kPairsPer - 1) / kPairsPer, 256, r.gcap);
   r.gh = grid_for((m + kCompactPer - 1) / kCompactPer, 256, r.gcap);
+  r.nchunks = (m + kBucketChunk - 1) / kBucketChunk;
+  r.sshift = slice_shift(n);
+  const int64_t units = (r.nchunks + kGroupChunks - 1) / kGroupChunks;
+  r.gq = (int)std::max<int64_t>(kSlices, std::min<int64_t>(units * kSlices,
+                                                           r.gcap / kSlices * kSlices));
 }
 
 void mark(CcRun& r, const char* phase) {
@@ -688,17 +867,23 @@ int cc_round(CcRun& r, int s) {
   hipLaunchKernelGGL(sv_mark, dim3(r.gv), dim3(256), 0, stream, D, b.NS, ni, b.w, s, b.ctl);
   mark(r, "sv1b_mark");
   if (r.m > 0) {
-    // round 1 reads the input pairs, later rounds the survivors of the last one
+    // round 1 sorts the input pairs by slice and hooks them; round 2 compacts
+    // the sorted pairs, later rounds the survivors of the last one
     int2* out = b.pairs[s & 1];
-    if (s == 1)
-      hipLaunchKernelGGL(sv_compact<true>, dim3(r.gh), dim3(256), 0, stream, r.es, r.ed,
-                         (const int2*)nullptr, r.m, (const unsigned long long*)nullptr, D, ni,
-                         out, b.mcount + s, b.w, s, b.ctl);
-    else
+    if (s == 1) {
+      hipLaunchKernelGGL(sv_bucket, dim3(r.gh), dim3(256), 0, stream, r.es, r.ed, r.m, ni,
+                         r.sshift, out, b.seg, b.w, b.ctl);
+      hipLaunchKernelGGL(sv_hook_first, dim3(r.gq), dim3(256), 0, stream, (const int2*)out,
+                         (const int32_t*)b.seg, r.nchunks, D);
+    } else if (s == 2) {
+      hipLaunchKernelGGL(sv_compact<true>, dim3(r.gq), dim3(256), 0, stream,
+                         (const int2*)b.pairs[1], (const unsigned long long*)nullptr,
+                         (const int32_t*)b.seg, r.nchunks, D, out, b.mcount + s, b.w, s);
+    } else {
       hipLaunchKernelGGL(sv_compact<false>, dim3(r.gh), dim3(256), 0, stream,
-                         (const int32_t*)nullptr, (const int32_t*)nullptr,
-                         (const int2*)b.pairs[(s - 1) & 1], r.m, b.mcount + (s - 1), D, ni, out,
-                         b.mcount + s, b.w, s, b.ctl);
+                         (const int2*)b.pairs[(s - 1) & 1], b.mcount + (s - 1),
+                         (const int32_t*)nullptr, (int64_t)0, D, out, b.mcount + s, b.w, s);
+    }
     mark(r, "compact");
     if (s > 1) {  // round 1's steps 2 and 3 are done by its compaction
       hipLaunchKernelGGL(sv_hook, dim3(r.gp), dim3(256), 0, stream, (const int2*)out,
