@@ -283,6 +283,7 @@ struct WalkArgs {
 // state.  The read and the write then touch the same cache line, which costs
 // far less than a write to a second random line.
 constexpr int kWalkBurst = 16;
+constexpr int kWalkChunk = 64;  // items a wave takes at a time
 
 template <bool kLevel0, bool kBatched, bool kPacked>
 __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
@@ -306,16 +307,34 @@ __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
   const int items = r + a.L;
   int* dyn = &ctl->lv[a.level].dyn;
   const uint32_t seed = a.seed;
-  // Work distribution: each workgroup owns a contiguous range of splitter
-  // ids and hands them to its lanes through an LDS counter.  (One global
-  // counter hit by every wave serialises at the memory side.)
+  // Work distribution.  One list, and the recursion levels: each workgroup
+  // owns a contiguous range of items (static splitters, then the virtual
+  // splitters at the list heads) and hands them to its lanes through an LDS
+  // counter.  A batch's level 0 (kChunks): its thousands of list heads come
+  // last and would all fall to the last workgroups, so each wave walks
+  // chunks of kWalkChunk items instead, first the chunk of its own index,
+  // then chunks taken from a device-wide counter with one atomic per chunk
+  // (4096 lists of 2^6..2^20 nodes: 17.1 -> 15.7 ms for the walk; for one
+  // list the counter costs more than it balances: the sequential 2^26 list,
+  // 8 M sublists, 0.6 -> 1.5 ms).  A counter hit at every refill of every
+  // wave would serialise at the memory side.
+  constexpr bool kChunks = kLevel0 && kBatched;
   __shared__ int wg_next;
-  const int per = (int)(((int64_t)items + gridDim.x - 1) / gridDim.x);
-  const int wg_lo = min(items, (int)((int64_t)blockIdx.x * per));
-  const int wg_hi = min(items, wg_lo + per);
-  if (threadIdx.x == 0) wg_next = wg_lo;
-  __syncthreads();
-  int* work = &wg_next;
+  int wg_hi = items;
+  if (!kChunks) {
+    const int per = (int)(((int64_t)items + gridDim.x - 1) / gridDim.x);
+    const int wg_lo = min(items, (int)((int64_t)blockIdx.x * per));
+    wg_hi = min(items, wg_lo + per);
+    if (threadIdx.x == 0) wg_next = wg_lo;
+    __syncthreads();
+  }
+  const int nwaves = (int)(((int64_t)gridDim.x * blockDim.x) / kWave);
+  const int wave_id = (int)(((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave);
+  int chunk_lo = (int)min<int64_t>(items, (int64_t)wave_id * kWalkChunk);
+  int chunk_hi = (int)min<int64_t>(items, (int64_t)chunk_lo + kWalkChunk);
+  bool drained = false;  // the device-wide counter has passed the last item
+  int* counter = &ctl->lv[a.level].work;
+  const int64_t dyn_base = (int64_t)nwaves * kWalkChunk;
 
   int sid = -1;       // sublist being walked, -1 = idle
   int x = 0;          // current node
@@ -331,15 +350,35 @@ __global__ void __launch_bounds__(1024) lr_walk(WalkArgs a) {
     const bool need = (sid < 0) & !retired;
     const uint64_t needm = __ballot(need);
     if (needm) {
-      const int leader = __builtin_ctzll(needm);
-      int first = 0;
-      if (lane_id() == leader) first = atomicAdd(work, __popcll(needm));
-      first = __shfl(first, leader);
-      if (need) {
-        const int item = first + lanes_below(needm);
-        if (item >= wg_hi) {
-          retired = true;
-        } else if (item < r) {  // static splitter
+      int first, avail;
+      if (kChunks) {
+        if (chunk_lo >= chunk_hi && !drained) {  // the wave's chunk is used up
+          int got = 0;
+          if (lane_id() == 0) got = atomicAdd(counter, kWalkChunk);
+          got = __shfl(got, 0);
+          const int64_t lo = dyn_base + got;
+          drained = lo >= items;
+          chunk_lo = drained ? items : (int)lo;
+          chunk_hi = drained ? items : (int)min<int64_t>(items, lo + kWalkChunk);
+        }
+        first = chunk_lo;
+        avail = chunk_hi - chunk_lo;
+        chunk_lo += min(avail, __popcll(needm));
+      } else {
+        const int leader = __builtin_ctzll(needm);
+        int f = 0;
+        if (lane_id() == leader) f = atomicAdd(&wg_next, __popcll(needm));
+        first = __shfl(f, leader);
+        avail = max(0, wg_hi - first);
+      }
+      // lanes past the end of the chunk (or range) wait for the next chunk,
+      // or retire once there is none
+      const int rank_in = lanes_below(needm);
+      if (need && rank_in >= avail) {
+        retired = kChunks ? drained : true;
+      } else if (need) {
+        const int item = first + rank_in;
+        if (item < r) {  // static splitter
           const int start = item << log2B;
           const int bsize = min(1 << log2B, N - start);
           x = start + (int)splitter_offset((uint32_t)item, seed, (uint32_t)bsize);
