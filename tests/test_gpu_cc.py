@@ -47,6 +47,45 @@ def test_planted_matches_oracle(pj, n, m, groups):
     assert len(np.unique(got)) == groups
 
 
+@pytest.mark.parametrize("case", ["one_larger_end", "one_slice", "tiny_ids", "ragged"])
+def test_slice_sorted_round_one_layouts(pj, case):
+    """Round 1 sorts each chunk of 2048 pairs by the slice of its larger end,
+    and the slice's workgroups take its runs of 8 chunks at a time: inputs
+    that put every pair in one slice (runs of whole chunks, units far above
+    2048 pairs), ids below one slice block, and a ragged last chunk."""
+    rng = np.random.default_rng(77)
+    if case == "one_larger_end":      # every pair's larger end is the same vertex
+        n, m = 300_000, 50_000
+        src = np.full(m, n - 1, dtype=np.int32)
+        dst = rng.integers(0, n - 1, m).astype(np.int32)
+    elif case == "one_slice":         # larger ends all inside one 1024-id block
+        n, m = 1 << 20, 60_000
+        src = rng.integers(5 * 1024, 6 * 1024, m).astype(np.int32)
+        dst = rng.integers(0, 5 * 1024, m).astype(np.int32)
+    elif case == "tiny_ids":          # n below one slice block: a single slice
+        n, m = 20, 10_000
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = rng.integers(0, n, m).astype(np.int32)
+    else:                             # self-loops, duplicates and a ragged tail
+        n, m = 77_777, 2048 * 37 + 5
+        src = rng.integers(0, n, m).astype(np.int32)
+        dst = src.copy()
+        keep = rng.random(m) < 0.7
+        dst[keep] = rng.integers(0, n, int(keep.sum()))
+    want = oracle.connected_components(src, dst, n)
+    assert np.array_equal(run(pj, src, dst, n), want), case
+    # and in a batch between two other graphs
+    a_s, a_d = W.random_graph(1000, 3000, 5)
+    c_s, c_d = W.random_graph(5000, 1000, 6)
+    voff = np.array([0, 1000, 1000 + n, 1000 + n + 5000], dtype=np.int64)
+    eoff = np.array([0, 3000, 3000 + m, 3000 + m + 1000], dtype=np.int64)
+    bs = np.concatenate([a_s, src, c_s]).astype(np.int32)
+    bd = np.concatenate([a_d, dst, c_d]).astype(np.int32)
+    got = pj.connected_components_batched(dev(bs), dev(bd), dev(voff), dev(eoff))
+    torch.cuda.synchronize()
+    assert np.array_equal(got.cpu().numpy(), oracle.connected_components_batched(bs, bd, voff, eoff))
+
+
 @pytest.mark.parametrize("family", ["lists", "trees2", "trees7", "path_up", "path_down", "star",
                                     "self_loops", "dense0.001", "dense0.01"])
 def test_graph_families(pj, family):
