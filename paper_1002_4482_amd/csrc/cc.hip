@@ -313,8 +313,12 @@ __device__ __forceinline__ int64_t unit_pos(const int* pre, const int64_t* start
 // end of one) or hooked onto (the smaller end), so step 3 finds no stagnant
 // root and the stamps of step 2 are never read: only the hooks are stored.
 // The workgroups of slice q store only into slice q's lines.  Plain stores:
-// D is not read in this kernel (the memory-model argument for them is given
-// with the library's design notes on store discipline).
+// D is not read in this kernel; an L2 writes back only the bytes stored, so
+// whichever of the concurrent stores to D[a] lands last, D[a] is a smaller
+// neighbour of a (the pointers form a forest of strictly decreasing ids),
+// and the kernel boundary makes every store visible to all XCDs.  Even a
+// store lost outright would only leave a a root for round 2 to hook, since
+// every pair survives into round 2.
 constexpr int kHookFirstPer = 12;
 
 __global__ void __launch_bounds__(256) sv_hook_first(const int2* __restrict__ pairs,
