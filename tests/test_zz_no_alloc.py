@@ -154,3 +154,29 @@ def test_no_pool_allocation(pj):
         pj.list_rank_noalloc(succ, out)
     torch.cuda.synchronize()
     assert pool.used_high() == 0
+
+
+def test_captured_in_a_graph_and_replayed(pj):
+    """The caller the entry point is for: a HIP graph captured around it
+    (torch.cuda.graph) and replayed several times, with eager work and new
+    inputs between the replays; every replay equals the oracle."""
+    n = 1_500_007
+    lists = [W.random_list(n, 50 + i) for i in range(3)]
+    d = dev(lists[0])
+    out = torch.full_like(d, -7)
+    pj.list_rank_noalloc(d, out)          # outside capture: plans and caches launch sizes
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        pj.list_rank_noalloc(d, out)
+    for i, succ in enumerate(lists):
+        d.copy_(torch.from_numpy(succ))
+        out.fill_(-7)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(out.cpu().numpy(), oracle.list_rank(succ)), i
+        # eager work between replays, on the same scratch
+        other = dev(W.random_list(70_001, 60 + i))
+        assert np.array_equal(pj.list_rank_noalloc(other).cpu().numpy(),
+                              oracle.list_rank(other.cpu().numpy())), i
