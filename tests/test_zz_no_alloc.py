@@ -180,3 +180,15 @@ def test_captured_in_a_graph_and_replayed(pj):
         other = dev(W.random_list(70_001, 60 + i))
         assert np.array_equal(pj.list_rank_noalloc(other).cpu().numpy(),
                               oracle.list_rank(other.cpu().numpy())), i
+
+
+@pytest.mark.parametrize("n", [0, 1, 2, 3, 64, 16_385])
+def test_small_and_degenerate_inputs(pj, n):
+    """n = 0 is a no-op, one node has rank 0; the one-workgroup path (up to
+    16 K nodes) and the first size above it, against the oracle."""
+    succ = W.random_list(n, 70 + n) if n else np.zeros(0, dtype=np.int32)
+    d = dev(succ)
+    out = torch.full((max(n, 1),), -7, dtype=torch.int32, device="cuda")[:n]
+    pj.list_rank_noalloc(d, out)
+    torch.cuda.synchronize()
+    assert np.array_equal(out.cpu().numpy(), oracle.list_rank(succ) if n else succ)
